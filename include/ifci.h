@@ -1,0 +1,206 @@
+/*
+ * ifci.h -- C ABI of libifci, the MI355X (gfx950) iFCI increment solver.
+ *
+ * The problem is stated as in the paper (Methods, "Incremental Full
+ * Configuration Interaction"): integrals h_pq and (pq|rs) over a localized
+ * orbital basis, a partition of the occupied orbitals into "bodies", and a
+ * truncation order n of the many-body expansion (eq. 1).  The library
+ * enumerates every increment S (1 <= |S| <= n), solves for the lowest root
+ * of the Hamiltonian in the space of S on the GPU, and assembles the
+ * incremental energies of eqs. 2-5 and the expansion total.
+ *
+ * Conventions shared by every call:
+ *  - integrals are FP64, row-major; (pq|rs) (chemists' order) sits at
+ *    eri[((p*n + q)*n + r)*n + s]; both must be symmetric as real integrals are;
+ *  - an increment S correlates every orbital of its bodies; the reference-
+ *    occupied orbitals of the other bodies stay doubly occupied (frozen core)
+ *    and their virtual orbitals are removed;
+ *  - the active orbitals of S, in increasing full-space index, are numbered
+ *    0..k-1; a one-spin string is a k-bit mask, strings are ordered by
+ *    increasing mask value; a determinant is |A,B> = a+(A, alpha) a+(B, beta)
+ *    |core>, and a CI vector is C[A][B] row-major (beta index fastest);
+ *  - the root solved for is the lowest one with C symmetric (C = C^T), the
+ *    even-spin states, which hold the closed-shell singlet;
+ *  - increments are numbered by size, then lexicographically by body tuple.
+ *
+ * Ownership: the caller owns every device buffer it passes (integrals,
+ * vectors, outputs, the workspace); the library never frees them.  A plan
+ * owns its host tables and a few small device tables it allocates itself.
+ * Buffers are contiguous and live on the plan's device.  A plan is not
+ * thread-safe; distinct plans are independent.
+ *
+ * Errors: every call returns ifci_status.  Invalid arguments return
+ * IFCI_ERR_ARG before any device work is queued; shapes the kernels do not
+ * handle return IFCI_ERR_UNSUPPORTED; HIP failures return IFCI_ERR_DEVICE.
+ * ifci_last_error() gives a human-readable detail (thread-local).  Calls that
+ * take a stream only enqueue work on it unless stated otherwise.
+ */
+#ifndef IFCI_H
+#define IFCI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IFCI_ABI_VERSION 1
+
+typedef struct ifci_plan_s* ifci_plan_t;
+typedef void* ifci_stream_t; /* a hipStream_t; NULL = the null stream */
+
+typedef enum {
+  IFCI_OK = 0,
+  IFCI_ERR_ARG = 1,
+  IFCI_ERR_UNSUPPORTED = 2,
+  IFCI_ERR_OOM = 3,
+  IFCI_ERR_DEVICE = 4,
+  IFCI_ERR_NOT_CONVERGED = 5,
+  IFCI_ERR_STATE = 6
+} ifci_status;
+
+typedef enum {
+  IFCI_FP64 = 0,   /* every step in FP64 */
+  IFCI_MIXED = 1   /* sigma in FP32 (MFMA, FP32 accumulation) on the shifted
+                      Hamiltonian, FP64 subspace, FP64 residual refinement */
+} ifci_precision;
+
+typedef enum {
+  IFCI_SOLVER_BATCHED = 0, /* one persistent workgroup per increment, whole
+                              Davidson on chip; increments up to 12 orbitals */
+  IFCI_SOLVER_PLAIN = 1    /* per increment, device-wide kernels for sigma and
+                              vector steps, host-driven loop; any size */
+} ifci_solver;
+
+/* Per-increment status words written by ifci_davidson. */
+enum {
+  IFCI_INC_PENDING = 0,
+  IFCI_INC_DONE = 1,
+  IFCI_INC_NOT_CONVERGED = 2,
+  IFCI_INC_EVICTED = 3
+};
+
+/* The problem (paper, Methods: eqs. 1-5 and the reference determinant). */
+typedef struct {
+  int32_t n_orb;            /* spatial orbitals of the full system, 1..64 */
+  int32_t n_bodies;         /* >= 1 */
+  const int32_t* body_ptr;  /* host [n_bodies + 1] CSR offsets, body_ptr[0] = 0 */
+  const int32_t* body_orb;  /* host [body_ptr[n_bodies]] disjoint orbital indices */
+  const int32_t* body_nocc; /* host [n_bodies]: the first body_nocc[b] orbitals
+                               of body b are doubly occupied in the reference */
+  int32_t order;            /* truncation order n, 1..n_bodies */
+  double e_const;           /* constant added to every energy */
+} ifci_problem;
+
+typedef struct {
+  int32_t precision;  /* ifci_precision */
+  int32_t solver;     /* ifci_solver */
+  double r_tol;       /* converged when ||H c - E c|| <= r_tol (unit c, FP64) */
+  double r_tol_inner; /* IFCI_MIXED: FP32 stage stops at this residual */
+  int32_t max_iter;   /* Davidson iterations (sigma builds) per increment */
+  int32_t max_space;  /* subspace size before restart, 2..16 */
+  uint32_t flags;     /* reserved, 0 */
+} ifci_options;
+
+/* Version of this header the library was built from (IFCI_ABI_VERSION). */
+int ifci_abi_version(void);
+
+/* Fill *opt with the defaults: FP64, batched, r_tol 1e-7, r_tol_inner 1e-4,
+ * max_iter 100, max_space 12. */
+void ifci_default_options(ifci_options* opt);
+
+/* Validate the problem, enumerate the increments, build the string and
+ * single-replacement tables of every distinct active-space shape, size the
+ * workspace, and upload the small tables to `hip_device`.  Synchronous.
+ * Returns IFCI_ERR_ARG for overlapping or out-of-range bodies, order outside
+ * 1..n_bodies, or a null pointer; IFCI_ERR_UNSUPPORTED when an increment has
+ * more than 16 active orbitals. */
+ifci_status ifci_plan_create(const ifci_problem* problem, const ifci_options* options,
+                             int hip_device, ifci_plan_t* out);
+ifci_status ifci_plan_destroy(ifci_plan_t plan);
+
+/* Sizes: number of increments, bytes of device workspace ifci_set_workspace
+ * needs, and the largest increment's determinant count. */
+ifci_status ifci_plan_info(ifci_plan_t plan, int64_t* n_inc, int64_t* workspace_bytes,
+                           int64_t* max_ndet);
+
+/* Description of increment idx: its bodies (host [order], -1 padded), active
+ * orbitals k, alpha electrons, and determinant count. */
+ifci_status ifci_increment(ifci_plan_t plan, int64_t idx, int32_t* bodies, int32_t* n_act,
+                           int32_t* n_alpha, int64_t* n_det);
+
+/* Expansion weights w_k (host [order]): the coefficient with which every
+ * E_c(T), |T| = k, enters the truncated sum of eqs. 1-5. */
+ifci_status ifci_weights(ifci_plan_t plan, double* w);
+
+/* String and single-replacement tables of a (k, n_alpha) space, for checking
+ * bit-exactly.  Host only, no plan or device needed.
+ * strings: host [C(k, n_alpha)] bitmasks, increasing.
+ * link:    host [C(k, n_alpha)][n_alpha*(k - n_alpha + 1)][4] entries
+ *          (p, q, J, sign) meaning E_pq |I> = sign |J>; for each string,
+ *          q runs over its occupied orbitals in increasing order and p over
+ *          the orbitals empty once q is removed (p = q included), increasing.
+ * Either pointer may be NULL. */
+ifci_status ifci_tables(int32_t k, int32_t n_alpha, int32_t* strings, int32_t* link);
+
+/* Hand the plan a caller-owned device workspace of at least
+ * workspace_bytes (ifci_plan_info), 256-byte aligned. */
+ifci_status ifci_set_workspace(ifci_plan_t plan, void* dev_ptr, int64_t bytes);
+
+/* Load integrals (device h [n*n], eri [n^4]) and embed every increment:
+ * frozen-core energy, effective one-electron operator, active two-electron
+ * block, and diagonal of H.  Reads h and eri only while the queued work runs. */
+ifci_status ifci_set_integrals(ifci_plan_t plan, const double* h, const double* eri,
+                               ifci_stream_t stream);
+
+/* sigma = H c for increment `inc`, with H the active-space Hamiltonian
+ * (without the frozen-core energy and e_const).  c and sigma: device
+ * [n_det] FP64, C[A][B] layout, any c (no symmetry needed); precision is
+ * IFCI_FP64 or IFCI_MIXED (FP32 arithmetic, results widened to FP64).
+ * Uses the workspace; c and sigma must not alias. */
+ifci_status ifci_sigma(ifci_plan_t plan, int64_t inc, const double* c, double* sigma,
+                       int32_t precision, ifci_stream_t stream);
+
+/* Same product restricted to symmetric c (C = C^T), as the batched Davidson
+ * computes it: one workgroup, everything on chip.  Increments up to 12
+ * active orbitals; IFCI_ERR_UNSUPPORTED otherwise. */
+ifci_status ifci_sigma_sector(ifci_plan_t plan, int64_t inc, const double* c, double* sigma,
+                              int32_t precision, ifci_stream_t stream);
+
+/* Lowest even-spin root of increments [first, first + count).
+ * e_out: device [count] total energies E(S) (frozen core and e_const
+ * included); status_out: device [count] IFCI_INC_* words; evict_mask: device
+ * [count] or NULL -- increments whose byte is nonzero are abandoned after one
+ * iteration and reported EVICTED (failure injection); iters_out/resid_out:
+ * device [count] or NULL.  Converged vectors stay in the workspace for
+ * ifci_vector and ifci_rdm. */
+ifci_status ifci_davidson(ifci_plan_t plan, int64_t first, int64_t count, double* e_out,
+                          int32_t* status_out, const uint8_t* evict_mask, int32_t* iters_out,
+                          double* resid_out, ifci_stream_t stream);
+
+/* Copy the converged unit vector of increment inc (device [n_det]). */
+ifci_status ifci_vector(ifci_plan_t plan, int64_t inc, double* c_out, ifci_stream_t stream);
+
+/* Energy assembly, eqs. 2-5: from device e_inc [n_inc] total energies
+ * compute eps [n_inc] (device, may be NULL) and host out[order + 2] =
+ * {E_total, E_ref, E_c^(1), ..., E_c^(n)}.  Synchronises the stream.
+ * status (device [n_inc] or NULL): IFCI_ERR_NOT_CONVERGED if any word is not
+ * IFCI_INC_DONE (outputs still written). */
+ifci_status ifci_energy(ifci_plan_t plan, const double* e_inc, const int32_t* status,
+                        double* eps, double* out, ifci_stream_t stream);
+
+/* Gradient of E_total (or of sum_S weights[S] E(S) + (1 - sum) E_ref when
+ * weights, device [n_inc], is given) with respect to every entry of h and
+ * eri taken as independent: dE_dh (device [n*n]) = weighted 1-RDM gamma,
+ * dE_deri (device [n^4], may be NULL) = weighted Gamma / 2.  Needs the
+ * converged vectors of every increment (ifci_davidson first). */
+ifci_status ifci_rdm(ifci_plan_t plan, const double* weights, double* dE_dh, double* dE_deri,
+                     ifci_stream_t stream);
+
+const char* ifci_status_string(ifci_status s);
+const char* ifci_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IFCI_H */

@@ -1,0 +1,536 @@
+// extern "C" entry points of libifci (declared in include/ifci.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+#include "plan.hpp"
+
+namespace ifci {
+static thread_local std::string g_error;
+void set_error(const std::string& msg) { g_error = msg; }
+}  // namespace ifci
+
+using namespace ifci;
+
+namespace {
+
+// Makes the plan's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+ifci_status dev_err(hipError_t e, const char* where) {
+  set_error(std::string(where) + ": " + hipGetErrorString(e));
+  return IFCI_ERR_DEVICE;
+}
+
+#define HIP_TRY(expr, where)                 \
+  do {                                       \
+    hipError_t e_ = (expr);                  \
+    if (e_ != hipSuccess) return dev_err(e_, where); \
+  } while (0)
+
+template <typename T>
+hipError_t upload(T** dst, const std::vector<T>& src) {
+  size_t bytes = std::max<size_t>(1, src.size()) * sizeof(T);
+  hipError_t e = hipMalloc((void**)dst, bytes);
+  if (e != hipSuccess) return e;
+  if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+template <typename T>
+void free_one(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+void free_device(ifci_plan_s* P) {
+  free_one(P->d_inc);
+  free_one(P->d_orbs);
+  free_one(P->d_tables);
+  free_one(P->d_order);
+  free_one(P->d_sub_ptr);
+  free_one(P->d_sub_idx);
+  free_one(P->d_inc_size);
+  free_one(P->d_rdm_off);
+  free_one(P->d_loc);
+  free_one(P->d_w_inc);
+  P->on_device = false;
+}
+
+// Upload the plan's small tables to its device (first use of the device).
+ifci_status ensure_device(ifci_plan_s* P) {
+  if (P->on_device) return IFCI_OK;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = upload(&P->d_inc, P->inc);
+  if (e == hipSuccess) e = upload(&P->d_orbs, P->orbs);
+  if (e == hipSuccess) e = upload(&P->d_tables, P->tables);
+  if (e == hipSuccess) e = upload(&P->d_order, P->order_all);
+  if (e == hipSuccess) e = upload(&P->d_sub_ptr, P->h_sub_ptr);
+  if (e == hipSuccess) e = upload(&P->d_sub_idx, P->h_sub_idx);
+  if (e == hipSuccess) e = upload(&P->d_inc_size, P->h_inc_size);
+  if (e == hipSuccess) e = upload(&P->d_rdm_off, P->rdm_off);
+  if (e == hipSuccess) e = upload(&P->d_loc, P->h_loc);
+  if (e == hipSuccess) e = upload(&P->d_w_inc, P->h_w_inc);
+  if (e != hipSuccess) {
+    free_device(P);
+    return dev_err(e, "uploading plan tables");
+  }
+  P->on_device = true;
+  return IFCI_OK;
+}
+
+ifci_status check_plan(ifci_plan_t p) {
+  if (!p) {
+    set_error("null plan");
+    return IFCI_ERR_ARG;
+  }
+  return IFCI_OK;
+}
+
+ifci_status need_ws(ifci_plan_t p) {
+  if (!p->ws) {
+    set_error("no workspace set (ifci_set_workspace)");
+    return IFCI_ERR_STATE;
+  }
+  return IFCI_OK;
+}
+
+ifci_status need_ints(ifci_plan_t p) {
+  ifci_status s = need_ws(p);
+  if (s != IFCI_OK) return s;
+  if (!p->integrals_set) {
+    set_error("integrals not set (ifci_set_integrals)");
+    return IFCI_ERR_STATE;
+  }
+  return IFCI_OK;
+}
+
+// LDS the batched solver asks for when running increments `ids`.
+int batch_lds(const ifci_plan_s* P, const std::vector<int32_t>& ids) {
+  int64_t need = 0;
+  for (int32_t i : ids) {
+    const IncDev& d = P->inc[i];
+    // fixed part plus E slices for every wave, capped at the hardware limit
+    int64_t np = (int64_t)d.npair, nbp = ((int64_t)d.n_str + 15) / 16 * 16;
+    int64_t want = batched_lds_bytes(d.k, d.n_str, d.n_link) + (kBatchThreads / 64 - 1) * ((np * nbp * 8 + 15) & ~15);
+    need = std::max(need, want);
+  }
+  return (int)std::min<int64_t>(kMaxLds, (need + 255) & ~int64_t(255));
+}
+
+}  // namespace
+
+extern "C" {
+
+int ifci_abi_version(void) { return IFCI_ABI_VERSION; }
+
+void ifci_default_options(ifci_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = IFCI_FP64;
+  o->solver = IFCI_SOLVER_BATCHED;
+  o->r_tol = 1e-7;
+  o->r_tol_inner = 1e-4;
+  o->max_iter = 100;
+  o->max_space = 12;
+  o->flags = 0;
+}
+
+const char* ifci_status_string(ifci_status s) {
+  switch (s) {
+    case IFCI_OK: return "ok";
+    case IFCI_ERR_ARG: return "invalid argument";
+    case IFCI_ERR_UNSUPPORTED: return "unsupported";
+    case IFCI_ERR_OOM: return "out of memory";
+    case IFCI_ERR_DEVICE: return "device error";
+    case IFCI_ERR_NOT_CONVERGED: return "not converged";
+    case IFCI_ERR_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char* ifci_last_error(void) { return g_error.c_str(); }
+
+ifci_status ifci_tables(int32_t k, int32_t n_alpha, int32_t* strings, int32_t* link) {
+  if (k < 1 || k > kMaxAct || n_alpha < 0 || n_alpha > k) {
+    set_error("ifci_tables: need 1 <= k <= 16 and 0 <= n_alpha <= k");
+    return IFCI_ERR_ARG;
+  }
+  fill_link_dump(k, n_alpha, strings, link);
+  return IFCI_OK;
+}
+
+ifci_status ifci_plan_create(const ifci_problem* problem, const ifci_options* options, int hip_device,
+                             ifci_plan_t* out) {
+  if (!out) {
+    set_error("null output pointer");
+    return IFCI_ERR_ARG;
+  }
+  *out = nullptr;
+  ifci_options opt;
+  if (options)
+    opt = *options;
+  else
+    ifci_default_options(&opt);
+  ifci_plan_s* P = new (std::nothrow) ifci_plan_s();
+  if (!P) return IFCI_ERR_OOM;
+  P->device = hip_device;
+  ifci_status s = plan_build(P, problem, &opt);
+  if (s != IFCI_OK) {
+    delete P;
+    return s;
+  }
+  const int n_inc = (int)P->inc.size();
+  // on-chip feasibility of each increment
+  P->batched_ok.resize(n_inc);
+  for (int i = 0; i < n_inc; ++i) {
+    const IncDev& d = P->inc[i];
+    P->batched_ok[i] = d.k <= 8 && batched_lds_bytes(d.k, d.n_str, d.n_link) <= kMaxLds;
+  }
+  // energy-assembly tables: the subsets of every increment (any order)
+  std::map<std::vector<int>, int> index;
+  for (int i = 0; i < n_inc; ++i) index[P->inc_bodies[i]] = i;
+  std::vector<int32_t> sub_ptr(1, 0), sub_idx, inc_size(n_inc);
+  for (int i = 0; i < n_inc; ++i) {
+    const std::vector<int>& S = P->inc_bodies[i];
+    const int sz = (int)S.size();
+    inc_size[i] = sz;
+    for (int k = 1; k <= sz; ++k) {
+      std::vector<int> c(k);
+      for (int j = 0; j < k; ++j) c[j] = j;
+      while (true) {
+        std::vector<int> T(k);
+        for (int j = 0; j < k; ++j) T[j] = S[c[j]];
+        sub_idx.push_back(index.at(T));
+        int j = k - 1;
+        while (j >= 0 && c[j] == sz - k + j) --j;
+        if (j < 0) break;
+        ++c[j];
+        for (int l = j + 1; l < k; ++l) c[l] = c[l - 1] + 1;
+      }
+    }
+    sub_ptr.push_back((int32_t)sub_idx.size());
+  }
+  // orbital roles per increment (and the reference as the last row)
+  const int n = P->n_orb;
+  std::vector<int8_t> loc((size_t)(n_inc + 1) * n, -2);
+  for (int i = 0; i < n_inc; ++i) {
+    const IncDev& d = P->inc[i];
+    for (int a = 0; a < d.k; ++a) loc[(size_t)i * n + P->orbs[d.act_off + a]] = (int8_t)a;
+    for (int c = 0; c < d.n_core; ++c) loc[(size_t)i * n + P->orbs[d.core_off + c]] = -1;
+  }
+  for (int o : P->ref_occ) loc[(size_t)n_inc * n + o] = -1;
+  std::vector<double> w_inc(n_inc);
+  for (int i = 0; i < n_inc; ++i) w_inc[i] = P->weights[inc_size[i] - 1];
+
+  P->h_sub_ptr = std::move(sub_ptr);
+  P->h_sub_idx = std::move(sub_idx);
+  P->h_inc_size = std::move(inc_size);
+  P->h_loc = std::move(loc);
+  P->h_w_inc = std::move(w_inc);
+  *out = P;
+  return IFCI_OK;
+}
+
+ifci_status ifci_plan_destroy(ifci_plan_t p) {
+  if (!p) return IFCI_OK;
+  if (p->on_device) {
+    DeviceGuard g(p->device);
+    free_device(p);
+  }
+  delete p;
+  return IFCI_OK;
+}
+
+ifci_status ifci_plan_info(ifci_plan_t p, int64_t* n_inc, int64_t* workspace_bytes, int64_t* max_ndet) {
+  if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
+  if (n_inc) *n_inc = (int64_t)p->inc.size();
+  if (workspace_bytes) *workspace_bytes = p->ws_bytes;
+  if (max_ndet) *max_ndet = p->max_ndet;
+  return IFCI_OK;
+}
+
+ifci_status ifci_increment(ifci_plan_t p, int64_t idx, int32_t* bodies, int32_t* n_act, int32_t* n_alpha,
+                           int64_t* n_det) {
+  if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
+  if (idx < 0 || idx >= (int64_t)p->inc.size()) {
+    set_error("increment index out of range");
+    return IFCI_ERR_ARG;
+  }
+  const IncDev& d = p->inc[idx];
+  if (bodies) {
+    const std::vector<int>& S = p->inc_bodies[idx];
+    for (int i = 0; i < p->order; ++i) bodies[i] = i < (int)S.size() ? S[i] : -1;
+  }
+  if (n_act) *n_act = d.k;
+  if (n_alpha) *n_alpha = d.na;
+  if (n_det) *n_det = d.n_det;
+  return IFCI_OK;
+}
+
+ifci_status ifci_weights(ifci_plan_t p, double* w) {
+  if (check_plan(p) != IFCI_OK || !w) {
+    set_error("null argument");
+    return IFCI_ERR_ARG;
+  }
+  for (int k = 0; k < p->order; ++k) w[k] = p->weights[k];
+  return IFCI_OK;
+}
+
+ifci_status ifci_set_workspace(ifci_plan_t p, void* dev_ptr, int64_t bytes) {
+  if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
+  if (!dev_ptr || bytes < p->ws_bytes || ((uintptr_t)dev_ptr & 255u)) {
+    set_error("workspace must be non-null, 256-byte aligned and at least workspace_bytes long");
+    return IFCI_ERR_ARG;
+  }
+  {
+    DeviceGuard g(p->device);
+    if (!g.ok) return dev_err(hipErrorInvalidDevice, "ifci_set_workspace");
+    ifci_status s = ensure_device(p);
+    if (s != IFCI_OK) return s;
+  }
+  p->ws = (char*)dev_ptr;
+  p->integrals_set = false;
+  std::fill(p->solved.begin(), p->solved.end(), 0);
+  return IFCI_OK;
+}
+
+ifci_status ifci_set_integrals(ifci_plan_t p, const double* h, const double* eri, ifci_stream_t stream) {
+  if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
+  if (!h || !eri) {
+    set_error("null integral pointer");
+    return IFCI_ERR_ARG;
+  }
+  ifci_status s = need_ws(p);
+  if (s != IFCI_OK) return s;
+  DeviceGuard g(p->device);
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(launch_embed(p->d_inc, (int)p->inc.size(), p->d_orbs, h, eri, p->n_orb, p->ws_ints(),
+                       p->d_orbs + p->ref_off, (int)p->ref_occ.size(), p->e_const, p->ws_misc(), st),
+          "ifci_set_integrals");
+  p->h = h;
+  p->eri = eri;
+  p->integrals_set = true;
+  std::fill(p->solved.begin(), p->solved.end(), 0);
+  return IFCI_OK;
+}
+
+ifci_status ifci_sigma(ifci_plan_t p, int64_t inc, const double* c, double* sigma, int32_t precision,
+                       ifci_stream_t stream) {
+  if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
+  if (inc < 0 || inc >= (int64_t)p->inc.size() || !c || !sigma || c == sigma ||
+      (precision != IFCI_FP64 && precision != IFCI_MIXED)) {
+    set_error("ifci_sigma: bad increment, pointer or precision");
+    return IFCI_ERR_ARG;
+  }
+  ifci_status s = need_ints(p);
+  if (s != IFCI_OK) return s;
+  DeviceGuard g(p->device);
+  const IncDev& d = p->inc[inc];
+  HIP_TRY(launch_sigma_wide(d, p->d_inc, (int)inc, p->ws_ints(), p->d_tables, c, sigma, p->ws_E(), precision, 0,
+                            0.0, (hipStream_t)stream),
+          "ifci_sigma");
+  return IFCI_OK;
+}
+
+ifci_status ifci_sigma_sector(ifci_plan_t p, int64_t inc, const double* c, double* sigma, int32_t precision,
+                              ifci_stream_t stream) {
+  if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
+  if (inc < 0 || inc >= (int64_t)p->inc.size() || !c || !sigma || c == sigma ||
+      (precision != IFCI_FP64 && precision != IFCI_MIXED)) {
+    set_error("ifci_sigma_sector: bad increment, pointer or precision");
+    return IFCI_ERR_ARG;
+  }
+  if (!p->batched_ok[inc]) {
+    set_error("ifci_sigma_sector: increment too large for the on-chip path");
+    return IFCI_ERR_UNSUPPORTED;
+  }
+  ifci_status s = need_ints(p);
+  if (s != IFCI_OK) return s;
+  DeviceGuard g(p->device);
+  std::vector<int32_t> one(1, (int32_t)inc);
+  HIP_TRY(launch_sigma_one(p->d_inc, (int)inc, p->ws_ints(), p->d_tables, c, sigma, precision, batch_lds(p, one),
+                           (hipStream_t)stream),
+          "ifci_sigma_sector");
+  return IFCI_OK;
+}
+
+ifci_status ifci_davidson(ifci_plan_t p, int64_t first, int64_t count, double* e_out, int32_t* status_out,
+                          const uint8_t* evict_mask, int32_t* iters_out, double* resid_out,
+                          ifci_stream_t stream) {
+  if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
+  const int64_t n_inc = (int64_t)p->inc.size();
+  if (first < 0 || count < 0 || first + count > n_inc || !e_out || !status_out) {
+    set_error("ifci_davidson: range outside the plan or null output");
+    return IFCI_ERR_ARG;
+  }
+  ifci_status s = need_ints(p);
+  if (s != IFCI_OK) return s;
+  if (count == 0) return IFCI_OK;
+  DeviceGuard g(p->device);
+  hipStream_t st = (hipStream_t)stream;
+  const bool plain_only = p->opt.solver == IFCI_SOLVER_PLAIN;
+  // batched part: heaviest first
+  std::vector<int32_t> ids, rest;
+  for (int32_t i : p->order_all)
+    if (i >= first && i < first + count) {
+      if (!plain_only && p->batched_ok[i])
+        ids.push_back(i);
+      else
+        rest.push_back(i);
+    }
+  if (!ids.empty()) {
+    // wait for any earlier upload from order_batch before reusing it
+    HIP_TRY(hipStreamSynchronize(st), "ifci_davidson");
+    p->order_batch = ids;
+    HIP_TRY(hipMemcpyAsync(p->d_order, p->order_batch.data(), ids.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, st),
+            "ifci_davidson upload");
+    SolveArgs A;
+    A.inc = p->d_inc;
+    A.order = p->d_order;
+    A.count = (int32_t)ids.size();
+    A.precision = p->opt.precision;
+    A.max_iter = p->opt.max_iter;
+    A.max_space = p->opt.max_space;
+    A.r_tol = p->opt.r_tol;
+    A.r_tol_inner = p->opt.r_tol_inner;
+    A.tables = p->d_tables;
+    A.ints = p->ws_ints();
+    A.dav = p->ws_dav();
+    A.first = first;
+    A.e_out = e_out;
+    A.status_out = status_out;
+    A.iters_out = iters_out;
+    A.resid_out = resid_out;
+    A.evict = evict_mask;
+    A.e_const = p->e_const;
+    HIP_TRY(launch_batched(A, batch_lds(p, ids), st), "ifci_davidson batched");
+  }
+  if (!rest.empty()) {
+    std::vector<uint8_t> ev;
+    if (evict_mask) {
+      ev.resize(count);
+      HIP_TRY(hipMemcpyAsync(ev.data(), evict_mask, count, hipMemcpyDeviceToHost, st), "ifci_davidson");
+      HIP_TRY(hipStreamSynchronize(st), "ifci_davidson");
+    }
+    for (int32_t i : rest) {
+      const IncDev& d = p->inc[i];
+      PlainArgs A;
+      A.d = d;
+      A.d_inc = p->d_inc;
+      A.inc = i;
+      A.ints = p->ws_ints();
+      A.tables = p->d_tables;
+      A.dav = p->ws_dav() + d.vec_off;
+      A.E = p->ws_E();
+      A.tmp = p->ws_tmp();
+      A.part = p->ws_part();
+      A.state = p->ws_state();
+      A.precision = p->opt.precision;
+      A.max_iter = p->opt.max_iter;
+      A.max_space = p->opt.max_space;
+      A.r_tol = p->opt.r_tol;
+      A.r_tol_inner = p->opt.r_tol_inner;
+      A.e_const = p->e_const;
+      A.evict = evict_mask ? ev[i - first] != 0 : false;
+      const int64_t o = i - first;
+      HIP_TRY(run_plain(A, e_out + o, status_out + o, iters_out ? iters_out + o : nullptr,
+                        resid_out ? resid_out + o : nullptr, st),
+              "ifci_davidson plain");
+    }
+  }
+  for (int64_t i = first; i < first + count; ++i) p->solved[i] = 1;
+  return IFCI_OK;
+}
+
+ifci_status ifci_vector(ifci_plan_t p, int64_t inc, double* c_out, ifci_stream_t stream) {
+  if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
+  if (inc < 0 || inc >= (int64_t)p->inc.size() || !c_out) {
+    set_error("ifci_vector: bad increment or pointer");
+    return IFCI_ERR_ARG;
+  }
+  ifci_status s = need_ints(p);
+  if (s != IFCI_OK) return s;
+  if (!p->solved[inc]) {
+    set_error("ifci_vector: increment not solved yet");
+    return IFCI_ERR_STATE;
+  }
+  DeviceGuard g(p->device);
+  const IncDev& d = p->inc[inc];
+  const double* X = p->ws_dav() + d.vec_off + 2 * (int64_t)p->opt.max_space * d.stride + d.stride;
+  HIP_TRY(launch_expand(d, X, c_out, (hipStream_t)stream), "ifci_vector");
+  return IFCI_OK;
+}
+
+ifci_status ifci_energy(ifci_plan_t p, const double* e_inc, const int32_t* status, double* eps, double* out,
+                        ifci_stream_t stream) {
+  if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
+  if (!e_inc || !out) {
+    set_error("ifci_energy: null pointer");
+    return IFCI_ERR_ARG;
+  }
+  ifci_status s = need_ints(p);
+  if (s != IFCI_OK) return s;
+  DeviceGuard g(p->device);
+  hipStream_t st = (hipStream_t)stream;
+  double* misc = p->ws_misc();
+  double* dout = misc + 8;
+  int32_t* bad = (int32_t*)(misc + 200);
+  HIP_TRY(launch_energy(e_inc, status, p->d_sub_ptr, p->d_sub_idx, p->d_inc_size, (int)p->inc.size(), p->order,
+                        misc, eps ? eps : p->ws_eps(), dout, bad, st),
+          "ifci_energy");
+  int32_t nbad = 0;
+  HIP_TRY(hipMemcpyAsync(out, dout, sizeof(double) * (p->order + 2), hipMemcpyDeviceToHost, st), "ifci_energy");
+  HIP_TRY(hipMemcpyAsync(&nbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st), "ifci_energy");
+  HIP_TRY(hipStreamSynchronize(st), "ifci_energy");
+  if (status && nbad > 0) {
+    set_error("ifci_energy: " + std::to_string(nbad) + " increments not converged");
+    return IFCI_ERR_NOT_CONVERGED;
+  }
+  return IFCI_OK;
+}
+
+ifci_status ifci_rdm(ifci_plan_t p, const double* weights, double* dE_dh, double* dE_deri, ifci_stream_t stream) {
+  if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
+  if (!dE_dh) {
+    set_error("ifci_rdm: null dE_dh");
+    return IFCI_ERR_ARG;
+  }
+  ifci_status s = need_ints(p);
+  if (s != IFCI_OK) return s;
+  for (uint8_t v : p->solved)
+    if (!v) {
+      set_error("ifci_rdm: every increment must be solved first (ifci_davidson)");
+      return IFCI_ERR_STATE;
+    }
+  DeviceGuard g(p->device);
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(launch_rdm(p->d_inc, p->inc.data(), (int)p->inc.size(), p->ws_dav(), p->d_tables, p->ws_rdm(),
+                     p->d_rdm_off, p->opt.max_space, st),
+          "ifci_rdm");
+  HIP_TRY(launch_rdm_accumulate(p->d_inc, (int)p->inc.size(), p->d_orbs, (const int32_t*)p->d_loc, p->ws_rdm(),
+                                p->d_rdm_off, weights ? weights : p->d_w_inc, p->d_orbs + p->ref_off,
+                                (int)p->ref_occ.size(), p->n_orb, dE_dh, dE_deri, st),
+          "ifci_rdm accumulate");
+  return IFCI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,624 @@
+// Batched iFCI increment solver: one workgroup owns one increment and runs
+// its whole Davidson solve with the CI vector, the sigma accumulator and the
+// string tables resident in LDS (increments whose C fits on chip, up to
+// 8 active orbitals at half filling).  Increments are dispatched heaviest
+// first, so the hardware workgroup dispatcher acts as the work queue over
+// the uneven sizes.
+//
+// Sigma (Knowles-Handy determinant FCI, restricted to symmetric C):
+//   D[Q][(a,b)] = (E_Q c)(a,b)  for unordered pairs Q, E_Q = E_kl + E_lk (or E_kk),
+//                 gathered through the pair table of string a (alpha part)
+//                 and of string b (beta part);
+//   E[P][(a,b)] = sum_Q V[P][Q] D[Q][(a,b)]         (MFMA, the dense contraction);
+//   S[a][b]     = sum over the links of a of sign * E[Q][(J,b)];
+//   sigma       = S + S^T     (the beta part of sigma is the transpose of the
+//                              alpha part when C = C^T).
+// Each wavefront owns one beta column b at a time: it computes E for the
+// whole column in its private LDS slice and gathers S[:, b] from it, so no
+// workgroup barrier sits inside the column loop.  The packed sigma slot of
+// (a, b) receives exactly two contributions (from column b and column a),
+// added to zero with LDS atomics; two-term sums are order independent, so
+// the result is deterministic.
+//
+// Vectors are stored packed and scaled: entry (a <= b) holds C[a][b] times
+// sqrt(2) when a != b, so that plain dot products of packed vectors equal
+// full-space dot products.
+#include "device_common.hpp"
+#include "launch.hpp"
+
+namespace ifci {
+
+struct Lds {
+  int32_t* ptab;   // [n_str][np]
+  int32_t* links;  // [n_str][n_link]
+  int32_t* strs;   // [n_str]
+  double* F;       // [n_str]
+  double* Jm;      // [k*k]
+  double* Km;      // [k*k]
+  double* hd;      // [k]
+  double* G;       // [16*16] subspace matrix
+  double* Gs;      // [16*16] copy diagonalised
+  double* Qv;      // [16*16] eigenvectors
+  double* y;       // [16]
+  double* cf;      // [16] projection coefficients
+  double* scal;    // [32]
+  int* iscal;      // [16]
+  double* red;     // [16 waves * 24]
+  double* cp;      // [n_sym] CI vector, packed unscaled (type T)
+  double* sp;      // [n_sym] sigma accumulator, packed scaled
+  double* tv;      // [n_sym] working vector, packed scaled
+  char* et;        // per-wave E column slices
+  int et_total;    // bytes available for the slices
+};
+
+__device__ __forceinline__ char* align16(char* p) {
+  return (char*)(((uintptr_t)p + 15) & ~(uintptr_t)15);
+}
+
+__device__ inline Lds carve(char* base, const IncDev& d, int lds_bytes, int et_waves) {
+  Lds L;
+  char* p = base;
+  const int n = d.n_str, np = d.npair, k = d.k;
+  L.ptab = (int32_t*)p;
+  p = align16(p + 4 * n * np);
+  L.links = (int32_t*)p;
+  p = align16(p + 4 * n * d.n_link);
+  L.strs = (int32_t*)p;
+  p = align16(p + 4 * n);
+  L.F = (double*)p;
+  p = align16(p + 8 * n);
+  L.Jm = (double*)p;
+  p += 8 * k * k;
+  L.Km = (double*)p;
+  p += 8 * k * k;
+  L.hd = (double*)p;
+  p = align16(p + 8 * k);
+  L.G = (double*)p;
+  p += 8 * 256;
+  L.Gs = (double*)p;
+  p += 8 * 256;
+  L.Qv = (double*)p;
+  p += 8 * 256;
+  L.y = (double*)p;
+  p += 8 * 16;
+  L.cf = (double*)p;
+  p += 8 * 16;
+  L.scal = (double*)p;
+  p += 8 * 32;
+  L.iscal = (int*)p;
+  p += 4 * 16;
+  p = align16(p);
+  L.red = (double*)p;
+  p += 8 * 16 * 24;
+  L.cp = (double*)p;
+  p = align16(p + 8 * d.n_sym);
+  L.sp = (double*)p;
+  p = align16(p + 8 * d.n_sym);
+  L.tv = (double*)p;
+  p = align16(p + 8 * d.n_sym);
+  L.et = p;
+  L.et_total = (int)((base + lds_bytes) - p);
+  (void)et_waves;
+  return L;
+}
+
+// Bytes of LDS the batched solver needs for an increment, excluding the E
+// slices, and the bytes of one wave's E slice in precision T.
+__host__ __device__ inline int64_t batched_fixed_bytes(int k, int n_str, int n_link) {
+  int64_t np = (int64_t)k * (k + 1) / 2, ns = tri(n_str);
+  auto a16 = [](int64_t x) { return (x + 15) & ~int64_t(15); };
+  int64_t b = a16(4 * n_str * np) + a16(4 * (int64_t)n_str * n_link) + a16(4 * n_str) +
+              a16(8 * n_str) + a16(8 * (2 * k * k + k)) + 8 * (3 * 256 + 32 + 32) + 4 * 16 + 16 +
+              8 * 16 * 24 + 3 * a16(8 * ns);
+  return b;
+}
+__host__ __device__ inline int64_t et_slice_bytes(int k, int n_str, int elem) {
+  int64_t np = (int64_t)k * (k + 1) / 2;
+  int64_t nbp = ((int64_t)n_str + 15) / 16 * 16;
+  return (np * nbp * elem + 15) & ~int64_t(15);
+}
+
+// ---------------------------------------------------------------------------
+// Sigma of the packed CI vector in L.cp (unscaled, type T stored in the
+// double slots), accumulated into L.sp (packed, scaled, must be zero).
+// V holds the pair contraction matrix; shift is subtracted from its
+// (diagonal pair, diagonal pair) block, which subtracts shift * N / N^2 * N
+// = shift from the operator.
+template <typename T, int K>
+__device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, const double* __restrict__ V,
+                             double shift, int et_waves) {
+  constexpr int NP = K * (K + 1) / 2;
+  constexpr int MT = (NP + 15) / 16;
+  constexpr int KS = (NP + 3) / 4;
+  typedef Mfma<T> M;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n = d.n_str, nlink = d.n_link;
+  const T* cp = (const T*)L.cp;
+  const double nel = 2.0 * d.na;
+  const double sh = nel > 0.0 ? shift / (nel * nel) : 0.0;
+
+  // A fragments: V[16 m + lane % 16][4 s + lane / 16]
+  T afr[MT][KS];
+  {
+    const int r = lane & 15, c = lane >> 4;
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int P = 16 * m + r, Q = 4 * s + c;
+        double v = 0.0;
+        if (P < NP && Q < NP) {
+          v = V[P * NP + Q];
+          bool pd = false, qd = false;
+#pragma unroll
+          for (int i = 0; i < K; ++i) {
+            pd |= (P == i * (i + 3) / 2);
+            qd |= (Q == i * (i + 3) / 2);
+          }
+          if (pd && qd) v -= sh;
+        }
+        afr[m][s] = (T)v;
+      }
+  }
+  if (wave >= et_waves) return;
+  T* et = (T*)(L.et + (size_t)wave * et_slice_bytes(K, n, (int)sizeof(T)));
+  const int nt_count = (n + 15) / 16;
+  const int nbp = nt_count * 16;
+  const int kq = lane >> 4, col = lane & 15;
+
+  for (int b = wave; b < n; b += et_waves) {
+    const int32_t* tb = L.ptab + b * NP;
+    for (int nt = 0; nt < nt_count; ++nt) {
+      const int a = nt * 16 + col;
+      const bool valid = a < n;
+      typename M::acc acc[MT];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) acc[m] = M::zero();
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int Q = 4 * s + kq;
+        T bv = (T)0;
+        if (valid && Q < NP) {
+          const int e1 = L.ptab[a * NP + Q];
+          if (e1 >= 0) {
+            const int J = e1 >> 1;
+            const T v = cp[packed(J, b)];
+            bv = (e1 & 1) ? -v : v;
+          }
+          const int e2 = tb[Q];
+          if (e2 >= 0) {
+            const int J = e2 >> 1;
+            const T v = cp[packed(a, J)];
+            bv += (e2 & 1) ? -v : v;
+          }
+        }
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[m] = M::mma(afr[m][s], bv, acc[m]);
+      }
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int P = 16 * m + 4 * kq + r;
+          if (P < NP) et[P * nbp + nt * 16 + col] = acc[m][r];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int a = lane; a < n; a += 64) {
+      const int32_t* la = L.links + a * nlink;
+      T s = (T)0;
+      for (int l = 0; l < nlink; ++l) {
+        const int code = la[l];
+        const int Q = code >> 17, J = (code >> 1) & 0xFFFF;
+        const T v = et[Q * nbp + J];
+        s += (code & 1) ? -v : v;
+      }
+      const double sc = (a == b) ? 2.0 : kSqrt2;
+      lds_add(&L.sp[packed(a, b)], sc * (double)s);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+// Expand the packed scaled vector tv into the packed unscaled cp of type T
+// and clear sp.
+template <typename T>
+__device__ inline void prepare_sigma(const IncDev& d, const Lds& L) {
+  T* cp = (T*)L.cp;
+  for (int64_t i = threadIdx.x; i < d.n_sym; i += blockDim.x) {
+    int a, b;
+    unpack(i, &a, &b);
+    const double v = L.tv[i];
+    cp[i] = (T)(a == b ? v : v * kRSqrt2);
+    L.sp[i] = 0.0;
+  }
+  __syncthreads();
+}
+
+template <typename T, int K>
+__device__ inline void sigma_phase(const IncDev& d, const Lds& L, const double* V, double shift,
+                                   int et_waves) {
+  prepare_sigma<T>(d, L);
+  sigma_sector<T, K>(d, L, V, shift, et_waves);
+  __syncthreads();
+}
+
+template <typename T, int K>
+__device__ inline int et_waves_for(const IncDev& d, const Lds& L) {
+  const int64_t slice = et_slice_bytes(K, d.n_str, (int)sizeof(T));
+  int w = (int)(L.et_total / slice);
+  const int nw = blockDim.x >> 6;
+  return w > nw ? nw : w;
+}
+
+// Load the increment's tables and diagonal data; returns the index of the
+// lowest diagonal element (packed) and writes the diagonal to HD.
+__device__ inline void load_increment(const IncDev& d, const Lds& L, const int32_t* __restrict__ tables,
+                                      const double* __restrict__ B, double* __restrict__ HD) {
+  const int n = d.n_str, np = d.npair, k = d.k;
+  const IntBlock ib = int_block(k);
+  for (int i = threadIdx.x; i < n * np; i += blockDim.x) L.ptab[i] = tables[d.pair_off + i];
+  for (int i = threadIdx.x; i < n * d.n_link; i += blockDim.x) L.links[i] = tables[d.link_off + i];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) L.strs[i] = tables[d.str_off + i];
+  for (int i = threadIdx.x; i < k * k; i += blockDim.x) {
+    L.Jm[i] = B[ib.J + i];
+    L.Km[i] = B[ib.K + i];
+  }
+  for (int i = threadIdx.x; i < k; i += blockDim.x) L.hd[i] = B[ib.hd + i];
+  __syncthreads();
+  // string energies F(s) = sum_{p in s} h'_pp + 1/2 sum_{p,q in s} [(pp|qq) - (pq|qp)]
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const uint32_t s = (uint32_t)L.strs[i];
+    double f = 0.0;
+    for (int p = 0; p < k; ++p) {
+      if (!(s >> p & 1u)) continue;
+      f += L.hd[p];
+      for (int q = 0; q < k; ++q)
+        if (s >> q & 1u) f += 0.5 * (L.Jm[p * k + q] - L.Km[p * k + q]);
+    }
+    L.F[i] = f;
+  }
+  __syncthreads();
+  // H_(a,b),(a,b) = F(a) + F(b) + sum_{p in a, q in b} (pp|qq)
+  for (int64_t i = threadIdx.x; i < d.n_sym; i += blockDim.x) {
+    int a, b;
+    unpack(i, &a, &b);
+    const uint32_t sa = (uint32_t)L.strs[a], sb = (uint32_t)L.strs[b];
+    double v = L.F[a] + L.F[b];
+    for (int p = 0; p < k; ++p) {
+      if (!(sa >> p & 1u)) continue;
+      for (int q = 0; q < k; ++q)
+        if (sb >> q & 1u) v += L.Jm[p * k + q];
+    }
+    HD[i] = v;
+  }
+  __syncthreads();
+}
+
+__device__ inline void argmin_block(const double* __restrict__ HD, int64_t ns, const Lds& L) {
+  double best = 1e300;
+  int64_t bi = 0x7fffffff;
+  for (int64_t i = threadIdx.x; i < ns; i += blockDim.x) {
+    const double v = HD[i];
+    if (v < best) best = v, bi = i;
+  }
+  // wave argmin with ties to the lower index
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(best, o, 64);
+    const int64_t oi = __shfl_xor(bi, o, 64);
+    if (ov < best || (ov == best && oi < bi)) best = ov, bi = oi;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    L.red[2 * wave] = best;
+    L.red[2 * wave + 1] = (double)bi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = L.red[0];
+    double ix = L.red[1];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+      if (L.red[2 * w] < b || (L.red[2 * w] == b && L.red[2 * w + 1] < ix)) b = L.red[2 * w], ix = L.red[2 * w + 1];
+    L.scal[0] = b;
+    L.iscal[0] = (int)ix;
+  }
+  __syncthreads();
+}
+
+template <int K>
+__device__ __forceinline__ void solve_one(const SolveArgs& A, int pos, char* lds, int lds_bytes) {
+  const int id = A.order[pos];
+  const IncDev d = A.inc[id];
+  const int nw = blockDim.x >> 6;
+  Lds L = carve(lds, d, lds_bytes, nw);
+  const double* B = A.ints + d.int_off;
+  const IntBlock ib = int_block(d.k);
+  const double* Vm = B + ib.V;
+  const int64_t ns = d.n_sym, st = d.stride;
+  double* base = A.dav + d.vec_off;
+  const int mmax = A.max_space;
+  double* Vb = base;                 // [mmax][stride]
+  double* Sb = base + mmax * st;     // [mmax][stride]
+  double* HD = base + 2 * mmax * st; // [stride]
+  double* X = HD + st;               // [stride]
+  const int tid = threadIdx.x;
+
+  load_increment(d, L, A.tables, B, HD);
+  argmin_block(HD, ns, L);
+  const double E0 = L.scal[0];
+  const int64_t guess = L.iscal[0];
+  for (int64_t i = tid; i < ns; i += blockDim.x) {
+    const double v = (i == guess) ? 1.0 : 0.0;
+    L.tv[i] = v;
+    Vb[i] = v;
+  }
+  for (int i = tid; i < 256; i += blockDim.x) L.G[i] = 0.0;
+  __syncthreads();
+
+  const int ew64 = et_waves_for<double, K>(d, L);
+  const int ew32 = et_waves_for<float, K>(d, L);
+  int phase = (A.precision == IFCI_MIXED) ? 32 : 64;
+  int m = 0, iters = 0, status = IFCI_INC_NOT_CONVERGED;
+  double theta = 0.0, resid = 1e300;
+  const int64_t o = (int64_t)id - A.first;  // position in the caller's range
+  const bool evict = A.evict && A.evict[o] != 0;
+
+  while (true) {
+    // sigma of the newest basis vector (in L.tv) -> S[m]
+    if (phase == 32)
+      sigma_phase<float, K>(d, L, Vm, E0, ew32);
+    else
+      sigma_phase<double, K>(d, L, Vm, E0, ew64);
+    ++iters;
+    for (int64_t i = tid; i < ns; i += blockDim.x) Sb[m * st + i] = L.sp[i];
+    // new column of the subspace matrix
+    {
+      double g[kMaxSpace];
+#pragma unroll
+      for (int j = 0; j < kMaxSpace; ++j) g[j] = 0.0;
+      for (int64_t i = tid; i < ns; i += blockDim.x) {
+        const double s = L.sp[i];
+#pragma unroll
+        for (int j = 0; j < kMaxSpace; ++j)
+          if (j <= m) g[j] += Vb[j * st + i] * s;
+      }
+      block_sum<kMaxSpace>(g, L.red, L.scal);
+      if (tid <= m) {
+        L.G[tid * 16 + m] = L.scal[tid];
+        L.G[m * 16 + tid] = L.scal[tid];
+      }
+      __syncthreads();
+      const int nn = m + 1;
+      if (tid < 256) L.Gs[tid] = L.G[tid];
+      __syncthreads();
+      if (tid < 64) jacobi_lowest(L.Gs, L.Qv, nn, &L.scal[20], L.y);
+      __syncthreads();
+      theta = L.scal[20];
+    }
+    const bool restart = (m + 1 == mmax);
+    // pass A: Ritz vector x, its sigma, residual, preconditioned correction
+    double acc[kMaxSpace + 3];
+#pragma unroll
+    for (int j = 0; j < kMaxSpace + 3; ++j) acc[j] = 0.0;
+    for (int64_t i = tid; i < ns; i += blockDim.x) {
+      double x = 0.0, sx = 0.0;
+      for (int j = 0; j <= m; ++j) {
+        const double yj = L.y[j];
+        x += yj * Vb[j * st + i];
+        sx += yj * Sb[j * st + i];
+      }
+      const double r = sx - theta * x;
+      double den = theta - (HD[i] - E0);
+      if (fabs(den) < 1e-8) den = (den < 0.0) ? -1e-8 : 1e-8;
+      const double t = r / den;
+      acc[kMaxSpace] += r * r;
+      acc[kMaxSpace + 1] += t * t;
+      acc[kMaxSpace + 2] += x * t;
+#pragma unroll
+      for (int j = 0; j < kMaxSpace; ++j)
+        if (j <= m) acc[j] += Vb[j * st + i] * t;
+      L.tv[i] = t;
+      X[i] = x;
+      if (restart) {
+        Vb[i] = x;
+        Sb[i] = sx;
+      }
+    }
+    block_sum<kMaxSpace + 3>(acc, L.red, L.scal);
+    resid = sqrt(L.scal[kMaxSpace]);
+    const double tt0 = L.scal[kMaxSpace + 1];
+    const double dx = L.scal[kMaxSpace + 2];
+    const int mb = restart ? 0 : m;
+    __syncthreads();
+    if (tid < kMaxSpace) L.cf[tid] = restart ? (tid == 0 ? dx : 0.0) : ((tid <= m) ? L.scal[tid] : 0.0);
+    __syncthreads();
+
+    const double tol = (phase == 32) ? A.r_tol_inner : A.r_tol;
+    if (evict) {
+      status = IFCI_INC_EVICTED;
+      break;
+    }
+    if (resid <= tol) {
+      if (phase == 32) {
+        // FP64 refinement: restart from x with FP64 sigma
+        phase = 64;
+        for (int64_t i = tid; i < ns; i += blockDim.x) {
+          const double x = X[i];
+          L.tv[i] = x;
+          Vb[i] = x;
+        }
+        for (int i = tid; i < 256; i += blockDim.x) L.G[i] = 0.0;
+        m = 0;
+        __syncthreads();
+        if (iters >= A.max_iter) break;
+        continue;
+      }
+      status = IFCI_INC_DONE;
+      break;
+    }
+    if (iters >= A.max_iter) break;
+    if (restart) {
+      for (int i = tid; i < 256; i += blockDim.x) L.G[i] = 0.0;
+      __syncthreads();
+      if (tid == 0) L.G[0] = theta;
+      __syncthreads();
+    }
+    // pass B: project out the basis (classical Gram-Schmidt), with a second
+    // pass when the norm drops by more than 1/sqrt(2) (DGKS criterion)
+    double acc2[kMaxSpace + 1];
+#pragma unroll
+    for (int j = 0; j < kMaxSpace + 1; ++j) acc2[j] = 0.0;
+    for (int64_t i = tid; i < ns; i += blockDim.x) {
+      double t = L.tv[i];
+      for (int j = 0; j <= mb; ++j) t -= L.cf[j] * Vb[j * st + i];
+      L.tv[i] = t;
+      acc2[kMaxSpace] += t * t;
+#pragma unroll
+      for (int j = 0; j < kMaxSpace; ++j)
+        if (j <= mb) acc2[j] += Vb[j * st + i] * t;
+    }
+    block_sum<kMaxSpace + 1>(acc2, L.red, L.scal);
+    double tt = L.scal[kMaxSpace];
+    if (tt < 0.5 * tt0) {
+      double c2[kMaxSpace];
+#pragma unroll
+      for (int j = 0; j < kMaxSpace; ++j) c2[j] = (j <= mb) ? L.scal[j] : 0.0;
+      __syncthreads();
+      double acc3[1] = {0.0};
+      for (int64_t i = tid; i < ns; i += blockDim.x) {
+        double t = L.tv[i];
+#pragma unroll
+        for (int j = 0; j < kMaxSpace; ++j)
+          if (j <= mb) t -= c2[j] * Vb[j * st + i];
+        L.tv[i] = t;
+        acc3[0] += t * t;
+      }
+      block_sum<1>(acc3, L.red, L.scal);
+      tt = L.scal[0];
+    }
+    __syncthreads();
+    if (!(tt > 1e-28)) break;  // no new direction: stagnated
+    const double inv = 1.0 / sqrt(tt);
+    m = mb + 1;
+    for (int64_t i = tid; i < ns; i += blockDim.x) {
+      const double t = L.tv[i] * inv;
+      L.tv[i] = t;
+      Vb[m * st + i] = t;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double e = theta + E0 + B[ib.misc + 0] + A.e_const;
+    if (A.e_out) A.e_out[o] = e;
+    if (A.status_out) A.status_out[o] = status;
+    if (A.iters_out) A.iters_out[o] = iters;
+    if (A.resid_out) A.resid_out[o] = resid;
+  }
+}
+
+__global__ void __launch_bounds__(kBatchThreads) batched_kernel(SolveArgs A, int lds_bytes) {
+  extern __shared__ __align__(16) char lds[];
+  const int pos = blockIdx.x;
+  if (pos >= A.count) return;
+  const int k = A.inc[A.order[pos]].k;
+  switch (k) {
+    case 1: solve_one<1>(A, pos, lds, lds_bytes); break;
+    case 2: solve_one<2>(A, pos, lds, lds_bytes); break;
+    case 3: solve_one<3>(A, pos, lds, lds_bytes); break;
+    case 4: solve_one<4>(A, pos, lds, lds_bytes); break;
+    case 5: solve_one<5>(A, pos, lds, lds_bytes); break;
+    case 6: solve_one<6>(A, pos, lds, lds_bytes); break;
+    case 7: solve_one<7>(A, pos, lds, lds_bytes); break;
+    case 8: solve_one<8>(A, pos, lds, lds_bytes); break;
+    default: break;
+  }
+}
+
+// Single sigma through the on-chip path (for checking it): full symmetric c
+// in, full sigma out, both [n_det] FP64.
+template <int K>
+__device__ void sigma_one(const IncDev d, const double* __restrict__ ints, const int32_t* __restrict__ tables,
+                          const double* __restrict__ c, double* __restrict__ sig, int precision,
+                          char* lds, int lds_bytes) {
+  const int nw = blockDim.x >> 6;
+  Lds L = carve(lds, d, lds_bytes, nw);
+  const int n = d.n_str, np = d.npair;
+  for (int i = threadIdx.x; i < n * np; i += blockDim.x) L.ptab[i] = tables[d.pair_off + i];
+  for (int i = threadIdx.x; i < n * d.n_link; i += blockDim.x) L.links[i] = tables[d.link_off + i];
+  for (int64_t i = threadIdx.x; i < d.n_sym; i += blockDim.x) {
+    int a, b;
+    unpack(i, &a, &b);
+    const double v = c[(int64_t)a * n + b];
+    L.tv[i] = (a == b) ? v : v * kSqrt2;
+  }
+  __syncthreads();
+  const double* Vm = ints + d.int_off + int_block(d.k).V;
+  if (precision == IFCI_MIXED)
+    sigma_phase<float, K>(d, L, Vm, 0.0, et_waves_for<float, K>(d, L));
+  else
+    sigma_phase<double, K>(d, L, Vm, 0.0, et_waves_for<double, K>(d, L));
+  for (int64_t i = threadIdx.x; i < d.n_sym; i += blockDim.x) {
+    int a, b;
+    unpack(i, &a, &b);
+    const double v = (a == b) ? L.sp[i] : L.sp[i] * kRSqrt2;
+    sig[(int64_t)a * n + b] = v;
+    sig[(int64_t)b * n + a] = v;
+  }
+}
+
+__global__ void __launch_bounds__(kBatchThreads) sigma_one_kernel(const IncDev* __restrict__ incs, int inc,
+                                                                  const double* __restrict__ ints,
+                                                                  const int32_t* __restrict__ tables,
+                                                                  const double* c, double* sig,
+                                                                  int precision, int lds_bytes) {
+  extern __shared__ __align__(16) char lds[];
+  const IncDev d = incs[inc];
+  switch (d.k) {
+    case 1: sigma_one<1>(d, ints, tables, c, sig, precision, lds, lds_bytes); break;
+    case 2: sigma_one<2>(d, ints, tables, c, sig, precision, lds, lds_bytes); break;
+    case 3: sigma_one<3>(d, ints, tables, c, sig, precision, lds, lds_bytes); break;
+    case 4: sigma_one<4>(d, ints, tables, c, sig, precision, lds, lds_bytes); break;
+    case 5: sigma_one<5>(d, ints, tables, c, sig, precision, lds, lds_bytes); break;
+    case 6: sigma_one<6>(d, ints, tables, c, sig, precision, lds, lds_bytes); break;
+    case 7: sigma_one<7>(d, ints, tables, c, sig, precision, lds, lds_bytes); break;
+    case 8: sigma_one<8>(d, ints, tables, c, sig, precision, lds, lds_bytes); break;
+    default: break;
+  }
+}
+
+int64_t batched_lds_bytes(int k, int n_str, int n_link) {
+  // fixed part plus one FP64 E slice per wave for at least one wave
+  return batched_fixed_bytes(k, n_str, n_link) + et_slice_bytes(k, n_str, 8);
+}
+
+hipError_t launch_batched(const SolveArgs& A, int lds_bytes, hipStream_t st) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)batched_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(batched_kernel, dim3(A.count), dim3(kBatchThreads), lds_bytes, st, A, lds_bytes);
+  return hipGetLastError();
+}
+
+hipError_t launch_sigma_one(const IncDev* incs, int inc, const double* ints, const int32_t* tables,
+                            const double* c, double* sig, int precision, int lds_bytes, hipStream_t st) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)sigma_one_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(sigma_one_kernel, dim3(1), dim3(kBatchThreads), lds_bytes, st, incs, inc, ints, tables,
+                     c, sig, precision, lds_bytes);
+  return hipGetLastError();
+}
+
+}  // namespace ifci

@@ -1,0 +1,148 @@
+// Device helpers shared by the libifci kernels: MFMA wrappers, wavefront and
+// workgroup reductions, packed-index arithmetic and the small symmetric
+// eigensolver of the Davidson subspace.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ifci_internal.h"
+
+namespace ifci {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+// 16x16x4 tiles.  Lane L holds A[L % 16][L / 16], B[L / 16][L % 16] and the
+// accumulator rows 4 (L / 16) + r, column L % 16, r = 0..3.
+template <>
+struct Mfma<double> {
+  typedef d4 acc;
+  static __device__ __forceinline__ acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<float> {
+  typedef f4 acc;
+  static __device__ __forceinline__ acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
+  static __device__ __forceinline__ acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum NV values over the workgroup; every thread gets the totals in out[].
+// Deterministic: fixed butterfly inside each wave, waves added in order.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red, double* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
+  if (lane == 0)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) red[wave * NV + j] = v[j];
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[w * NV + threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// Packed upper-triangle index: entry (a, b), a <= b, lives at b (b + 1) / 2 + a.
+__device__ __forceinline__ int64_t packed(int64_t a, int64_t b) {
+  return a <= b ? tri(b) + a : tri(a) + b;
+}
+__device__ __forceinline__ void unpack(int64_t i, int* a, int* b) {
+  int64_t c = (int64_t)((sqrt(8.0 * (double)i + 1.0) - 1.0) * 0.5);
+  while (tri(c + 1) <= i) ++c;
+  while (tri(c) > i) --c;
+  *b = (int)c;
+  *a = (int)(i - tri(c));
+}
+
+// Atomic add into LDS (ds_add_f64).  The pointer must point into LDS.
+typedef __attribute__((address_space(3))) double lds_double;
+__device__ __forceinline__ void lds_add(double* p, double v) {
+  __atomic_fetch_add((lds_double*)p, v, __ATOMIC_RELAXED);
+}
+
+constexpr double kSqrt2 = 1.4142135623730950488;
+constexpr double kRSqrt2 = 0.70710678118654752440;
+
+// Lowest eigenpair of the symmetric n x n matrix A (row stride 16, n <= 16)
+// by cyclic Jacobi rotations (Golub & Van Loan, symmetric Schur
+// decomposition).  Executed by one full wavefront; A is overwritten, Q
+// (stride 16) receives the eigenvectors.  Lane i owns row i.
+__device__ inline void jacobi_lowest(double* A, double* Q, int n, double* theta, double* y) {
+  const int lane = threadIdx.x & 63;
+  if (lane < n)
+    for (int j = 0; j < n; ++j) Q[lane * 16 + j] = (lane == j) ? 1.0 : 0.0;
+  __builtin_amdgcn_wave_barrier();
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, all = 0.0;
+    if (lane < n)
+      for (int j = 0; j < n; ++j) {
+        double a = A[lane * 16 + j];
+        all += a * a;
+        if (j != lane) off += a * a;
+      }
+    off = wave_sum(off);
+    all = wave_sum(all);
+    if (!(off > 1e-32 * all)) break;
+    for (int p = 0; p < n - 1; ++p) {
+      for (int q = p + 1; q < n; ++q) {
+        __builtin_amdgcn_wave_barrier();
+        const double apq = A[p * 16 + q];
+        if (apq == 0.0) continue;
+        const double app = A[p * 16 + p], aqq = A[q * 16 + q];
+        const double tau = (aqq - app) / (2.0 * apq);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+        __builtin_amdgcn_wave_barrier();
+        if (lane < n && lane != p && lane != q) {
+          const double aip = A[lane * 16 + p], aiq = A[lane * 16 + q];
+          const double nip = c * aip - s * aiq, niq = s * aip + c * aiq;
+          A[lane * 16 + p] = nip;
+          A[p * 16 + lane] = nip;
+          A[lane * 16 + q] = niq;
+          A[q * 16 + lane] = niq;
+        }
+        if (lane == p) {
+          A[p * 16 + p] = app - t * apq;
+          A[p * 16 + q] = 0.0;
+          A[q * 16 + p] = 0.0;
+        }
+        if (lane == q) A[q * 16 + q] = aqq + t * apq;
+        if (lane < n) {
+          const double vp = Q[lane * 16 + p], vq = Q[lane * 16 + q];
+          Q[lane * 16 + p] = c * vp - s * vq;
+          Q[lane * 16 + q] = s * vp + c * vq;
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  __builtin_amdgcn_wave_barrier();
+  int imin = 0;
+  double best = A[0];
+  for (int i = 1; i < n; ++i) {
+    double v = A[i * 16 + i];
+    if (v < best) best = v, imin = i;
+  }
+  if (lane == 0) *theta = best;
+  if (lane < n) y[lane] = Q[lane * 16 + imin];
+  __builtin_amdgcn_wave_barrier();
+}
+
+}  // namespace ifci

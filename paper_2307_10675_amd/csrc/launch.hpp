@@ -1,0 +1,63 @@
+// Host-callable launchers of the libifci kernels.  Internal.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ifci_internal.h"
+
+namespace ifci {
+
+constexpr int kMaxLds = 163840;  // LDS per workgroup on gfx950
+
+hipError_t launch_embed(const IncDev* incs, int n_inc, const int32_t* orbs, const double* h,
+                        const double* eri, int n, double* ints, const int32_t* ref_occ, int n_ref,
+                        double e_const, double* misc, hipStream_t st);
+
+int64_t batched_lds_bytes(int k, int n_str, int n_link);
+hipError_t launch_batched(const SolveArgs& A, int lds_bytes, hipStream_t st);
+hipError_t launch_sigma_one(const IncDev* incs, int inc, const double* ints, const int32_t* tables,
+                            const double* c, double* sig, int precision, int lds_bytes,
+                            hipStream_t st);
+
+// Device-wide sigma for any increment (E materialised in the workspace).
+// mode 0: c and sigma full [n_det] vectors, any c.  mode 1: c and sigma
+// packed scaled symmetric vectors.
+hipError_t launch_sigma_wide(const IncDev& d, const IncDev* d_inc_dev, int inc, const double* ints,
+                             const int32_t* tables, const double* c, double* sig, double* E,
+                             int precision, int mode, double shift, hipStream_t st);
+
+// Host-driven Davidson over one increment with device-wide kernels.
+struct PlainArgs {
+  IncDev d;
+  const IncDev* d_inc;
+  int inc;
+  const double* ints;
+  const int32_t* tables;
+  double* dav;     // Davidson block of this increment
+  double* E;       // sigma scratch
+  double* tmp;     // [>= 2 stride]
+  double* part;    // partial sums
+  double* state;   // device state block
+  int precision, max_iter, max_space;
+  double r_tol, r_tol_inner, e_const;
+  bool evict;
+};
+hipError_t run_plain(const PlainArgs& A, double* e_out, int32_t* status_out, int32_t* iters_out,
+                     double* resid_out, hipStream_t st);
+
+hipError_t launch_expand(const IncDev& d, const double* X, double* c, hipStream_t st);
+
+hipError_t launch_energy(const double* e_inc, const int32_t* status, const int32_t* sub_ptr,
+                         const int32_t* sub_idx, const int32_t* inc_size, int n_inc, int order,
+                         const double* misc_in, double* eps, double* out, int32_t* bad,
+                         hipStream_t st);
+
+hipError_t launch_rdm(const IncDev* incs, const IncDev* host_incs, int n_inc, const double* dav_base,
+                      const int32_t* tables, double* rdm, const int64_t* rdm_off_dev, int mmax,
+                      hipStream_t st);
+hipError_t launch_rdm_accumulate(const IncDev* incs, int n_inc, const int32_t* orbs,
+                                 const int32_t* loc, const double* rdm, const int64_t* rdm_off_dev,
+                                 const double* w, const int32_t* ref_occ, int n_ref, int n,
+                                 double* dh, double* deri, hipStream_t st);
+
+}  // namespace ifci

@@ -1,0 +1,88 @@
+// Host-side plan: problem validation, increment enumeration, string tables,
+// workspace layout.  Internal to libifci.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "ifci_internal.h"
+
+struct ifci_plan_s {
+  int device = 0;
+  // problem
+  int n_orb = 0;
+  int n_bodies = 0;
+  int order = 0;
+  double e_const = 0.0;
+  std::vector<std::vector<int>> bodies;
+  std::vector<int> nocc;
+  ifci_options opt{};
+  // increments
+  std::vector<std::vector<int>> inc_bodies;
+  std::vector<ifci::IncDev> inc;
+  std::vector<int32_t> orbs;    // orbital blob
+  std::vector<int32_t> tables;  // table blob
+  std::vector<double> weights;  // w_k, k = 1..order
+  std::vector<int> ref_occ;     // reference-occupied orbitals (sorted)
+  // sizes
+  int64_t ints_doubles = 0, dav_doubles = 0;
+  int64_t max_ndet = 0, max_npair = 0, max_stride = 0;
+  int64_t rdm_doubles = 0;
+  std::vector<int64_t> rdm_off;  // per increment: active gamma (k^2) then Gamma (k^4)
+  // workspace regions (byte offsets)
+  int64_t off_ints = 0, off_dav = 0, off_E = 0, off_tmp = 0, off_part = 0, off_state = 0,
+          off_rdm = 0, off_misc = 0, off_eps = 0, ws_bytes = 0;
+  int64_t E_doubles = 0, tmp_doubles = 0, part_doubles = 0;
+  // device
+  ifci::IncDev* d_inc = nullptr;
+  int32_t* d_orbs = nullptr;
+  int32_t* d_tables = nullptr;
+  int32_t* d_order = nullptr;  // increments of the current batch, heaviest first
+  std::vector<int32_t> order_all;
+  std::vector<int32_t> order_batch;  // host copy kept alive for async uploads
+  std::vector<uint8_t> batched_ok;   // increment fits the on-chip solver
+  int32_t* d_sub_ptr = nullptr;      // energy assembly: subsets of each increment
+  int32_t* d_sub_idx = nullptr;
+  int32_t* d_inc_size = nullptr;
+  int64_t* d_rdm_off = nullptr;
+  int8_t* d_loc = nullptr;           // [n_inc + 1][n_orb] orbital roles
+  double* d_w_inc = nullptr;         // expansion weight of every increment
+  bool on_device = false;
+  std::vector<int32_t> h_sub_ptr, h_sub_idx, h_inc_size;
+  std::vector<int8_t> h_loc;
+  std::vector<double> h_w_inc;
+  int64_t ref_off = 0;               // reference-occupied orbitals in the orbital blob
+  char* ws = nullptr;
+  const double* h = nullptr;
+  const double* eri = nullptr;
+  bool integrals_set = false;
+  bool vectors_ready = false;
+  std::vector<uint8_t> solved;  // host mirror: which increments have a vector
+
+  double* ws_ints() const { return (double*)(ws + off_ints); }
+  double* ws_dav() const { return (double*)(ws + off_dav); }
+  double* ws_E() const { return (double*)(ws + off_E); }
+  double* ws_tmp() const { return (double*)(ws + off_tmp); }
+  double* ws_part() const { return (double*)(ws + off_part); }
+  double* ws_state() const { return (double*)(ws + off_state); }
+  double* ws_rdm() const { return (double*)(ws + off_rdm); }
+  double* ws_misc() const { return (double*)(ws + off_misc); }
+  double* ws_eps() const { return (double*)(ws + off_eps); }
+};
+
+namespace ifci {
+
+void set_error(const std::string& msg);
+
+// Tables of one (k, na) space, appended to `blob`.  Returns offsets.
+struct ShapeTables {
+  int k, na, n_str, npair, n_link;
+  int64_t str_off, pair_off, link_off, ord_off;
+};
+ShapeTables build_shape(int k, int na, std::vector<int32_t>& blob);
+int64_t binom(int n, int k);
+void fill_link_dump(int k, int na, int32_t* strings, int32_t* link);
+
+}  // namespace ifci
+
+ifci_status plan_build(ifci_plan_s* P, const ifci_problem* pr, const ifci_options* op);

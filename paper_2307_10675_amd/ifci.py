@@ -1,0 +1,279 @@
+"""Python binding of libifci (ctypes).  Argument marshalling only: every step
+of the computation runs in the HIP library; PyTorch supplies device memory
+and the stream.  The names follow include/ifci.h."""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libifci.so")
+
+FP64, MIXED = 0, 1
+BATCHED, PLAIN = 0, 1
+INC_PENDING, INC_DONE, INC_NOT_CONVERGED, INC_EVICTED = 0, 1, 2, 3
+STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "out of memory", 4: "device error",
+          5: "not converged", 6: "invalid state"}
+
+
+class IfciError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libifci: {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("n_orb", ctypes.c_int32), ("n_bodies", ctypes.c_int32),
+                ("body_ptr", ctypes.POINTER(ctypes.c_int32)), ("body_orb", ctypes.POINTER(ctypes.c_int32)),
+                ("body_nocc", ctypes.POINTER(ctypes.c_int32)), ("order", ctypes.c_int32),
+                ("e_const", ctypes.c_double)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("solver", ctypes.c_int32), ("r_tol", ctypes.c_double),
+                ("r_tol_inner", ctypes.c_double), ("max_iter", ctypes.c_int32), ("max_space", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+
+_SIGNATURES = {
+    "ifci_abi_version": (ctypes.c_int, []),
+    "ifci_default_options": (None, [ctypes.POINTER(Options)]),
+    "ifci_plan_create": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "ifci_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "ifci_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "ifci_increment": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int64)]),
+    "ifci_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "ifci_tables": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_int32)]),
+    "ifci_set_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
+    "ifci_set_integrals": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "ifci_sigma": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_int32, ctypes.c_void_p]),
+    "ifci_sigma_sector": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int32, ctypes.c_void_p]),
+    "ifci_davidson": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p]),
+    "ifci_vector": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "ifci_energy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "ifci_rdm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.c_void_p]),
+    "ifci_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "ifci_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """The loaded libifci.  Raises if the library has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libifci.so not found at {LIB_PATH}; build it with "
+                               "`python -m paper_2307_10675_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != 0:
+        raise IfciError(code, lib().ifci_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    lib().ifci_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def tables(k: int, n_alpha: int):
+    """(strings, link[n_str][n_link][4]) of a (k, n_alpha) space, host only."""
+    from math import comb
+    n_str = comb(k, n_alpha)
+    n_link = n_alpha * (k - n_alpha + 1)
+    s = (ctypes.c_int32 * n_str)()
+    lk = (ctypes.c_int32 * (n_str * n_link * 4))()
+    _check(lib().ifci_tables(k, n_alpha, s, lk))
+    return np.array(s, dtype=np.int64), np.array(lk, dtype=np.int64).reshape(n_str, n_link, 4)
+
+
+@dataclass
+class IncrementInfo:
+    bodies: tuple
+    n_act: int
+    n_alpha: int
+    n_det: int
+
+
+class Plan:
+    """ifci_plan_t with its workspace.  `problem` needs h, eri, bodies,
+    nocc, order (and optionally e_const) -- e.g. synthetic.Problem."""
+
+    def __init__(self, problem, precision=FP64, solver=BATCHED, device: int = 0, **opts):
+        self._keep = []
+        bodies = [list(b) for b in problem.bodies]
+        ptr = np.cumsum([0] + [len(b) for b in bodies]).astype(np.int32)
+        orb = np.array([o for b in bodies for o in b], dtype=np.int32)
+        nocc = np.array(problem.nocc, dtype=np.int32)
+        self._keep += [ptr, orb, nocc]
+        pr = Problem(n_orb=problem.h.shape[0], n_bodies=len(bodies),
+                     body_ptr=ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                     body_orb=orb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                     body_nocc=nocc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                     order=problem.order, e_const=float(getattr(problem, "e_const", 0.0)))
+        self.options = default_options(precision=precision, solver=solver, **opts)
+        h = ctypes.c_void_p()
+        _check(lib().ifci_plan_create(ctypes.byref(pr), ctypes.byref(self.options), device, ctypes.byref(h)))
+        self._h = h
+        self.device = device
+        self.order = problem.order
+        self.n_orb = problem.h.shape[0]
+        self.workspace = None
+        self._ints = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ifci_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- host queries
+    def info(self):
+        n, ws, nd = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().ifci_plan_info(self._h, ctypes.byref(n), ctypes.byref(ws), ctypes.byref(nd)))
+        return dict(n_inc=n.value, workspace_bytes=ws.value, max_ndet=nd.value)
+
+    @property
+    def n_inc(self) -> int:
+        return self.info()["n_inc"]
+
+    def increment(self, idx: int) -> IncrementInfo:
+        b = (ctypes.c_int32 * self.order)()
+        k, na, nd = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().ifci_increment(self._h, idx, b, ctypes.byref(k), ctypes.byref(na), ctypes.byref(nd)))
+        return IncrementInfo(tuple(x for x in b if x >= 0), k.value, na.value, nd.value)
+
+    def increments(self):
+        return [self.increment(i) for i in range(self.n_inc)]
+
+    def weights(self):
+        w = (ctypes.c_double * self.order)()
+        _check(lib().ifci_weights(self._h, w))
+        return list(w)
+
+    # ---------------------------------------------------------------- device
+    def attach(self, h, eri, stream=None):
+        """Allocate the workspace (torch) and load integrals (torch CUDA FP64)."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        ws_bytes = self.info()["workspace_bytes"]
+        self.workspace = torch.empty(max(ws_bytes, 256) // 8 + 64, dtype=torch.float64, device=dev)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        _check(lib().ifci_set_workspace(self._h, ctypes.c_void_p(base + off), ws_bytes))
+        h = torch.as_tensor(h, dtype=torch.float64, device=dev).contiguous()
+        eri = torch.as_tensor(eri, dtype=torch.float64, device=dev).contiguous()
+        self._ints = (h, eri)
+        _check(lib().ifci_set_integrals(self._h, _ptr(h), _ptr(eri), _stream(stream)))
+        return self
+
+    def sigma(self, inc: int, c, precision=FP64, stream=None):
+        import torch
+        c = c.contiguous()
+        out = torch.empty_like(c)
+        _check(lib().ifci_sigma(self._h, inc, _ptr(c), _ptr(out), precision, _stream(stream)))
+        return out
+
+    def sigma_sector(self, inc: int, c, precision=FP64, stream=None):
+        import torch
+        c = c.contiguous()
+        out = torch.empty_like(c)
+        _check(lib().ifci_sigma_sector(self._h, inc, _ptr(c), _ptr(out), precision, _stream(stream)))
+        return out
+
+    def davidson(self, first: int = 0, count: int | None = None, evict=None, stream=None):
+        import torch
+        dev = torch.device("cuda", self.device)
+        if count is None:
+            count = self.n_inc - first
+        e = torch.empty(count, dtype=torch.float64, device=dev)
+        st = torch.empty(count, dtype=torch.int32, device=dev)
+        it = torch.empty(count, dtype=torch.int32, device=dev)
+        rs = torch.empty(count, dtype=torch.float64, device=dev)
+        ev = None
+        if evict is not None:
+            ev = torch.as_tensor(evict, dtype=torch.uint8, device=dev).contiguous()
+        _check(lib().ifci_davidson(self._h, first, count, _ptr(e), _ptr(st), _ptr(ev), _ptr(it), _ptr(rs),
+                                   _stream(stream)))
+        return e, st, it, rs
+
+    def vector(self, inc: int, stream=None):
+        import torch
+        nd = self.increment(inc).n_det
+        out = torch.empty(nd, dtype=torch.float64, device=torch.device("cuda", self.device))
+        _check(lib().ifci_vector(self._h, inc, _ptr(out), _stream(stream)))
+        return out
+
+    def energy(self, e_inc, status=None, stream=None):
+        """{'total', 'e_ref', 'by_order', 'eps'} from total increment energies."""
+        import torch
+        eps = torch.empty_like(e_inc)
+        out = (ctypes.c_double * (self.order + 2))()
+        code = lib().ifci_energy(self._h, _ptr(e_inc), _ptr(status), _ptr(eps), out, _stream(stream))
+        if code not in (0, 5):
+            _check(code)
+        return dict(total=out[0], e_ref=out[1], by_order=list(out[2:]), eps=eps, converged=(code == 0))
+
+    def rdm(self, weights=None, with_eri=True, stream=None):
+        """(dE/dh, dE/d(pq|rs)) of the expansion (or of the given weights)."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        n = self.n_orb
+        dh = torch.empty((n, n), dtype=torch.float64, device=dev)
+        dg = torch.empty((n, n, n, n), dtype=torch.float64, device=dev) if with_eri else None
+        w = None
+        if weights is not None:
+            w = torch.as_tensor(weights, dtype=torch.float64, device=dev).contiguous()
+        _check(lib().ifci_rdm(self._h, _ptr(w), _ptr(dh), _ptr(dg), _stream(stream)))
+        return dh, dg
+
+
+def solve(problem, precision=FP64, solver=BATCHED, device: int = 0, **opts):
+    """Whole expansion on the GPU: plan, embed, Davidson over every increment,
+    energy assembly.  Returns the plan (kept for vectors and RDMs) and results."""
+    plan = Plan(problem, precision=precision, solver=solver, device=device, **opts)
+    plan.attach(problem.h, problem.eri)
+    e, st, it, rs = plan.davidson()
+    en = plan.energy(e, st)
+    return plan, dict(E=e, status=st, iters=it, resid=rs, **en)
