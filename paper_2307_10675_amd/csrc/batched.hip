@@ -41,6 +41,8 @@ struct Lds {
   double* Qv;      // [16*16] eigenvectors
   double* y;       // [16]
   double* cf;      // [16] projection coefficients
+  double* ev;      // [16] sorted subspace eigenvalues
+  int* perm;       // [16] their eigenvector columns
   double* scal;    // [32]
   int* iscal;      // [16]
   double* red;     // [16 waves * 24]
@@ -83,6 +85,10 @@ __device__ inline Lds carve(char* base, const IncDev& d, int lds_bytes, int et_w
   p += 8 * 16;
   L.cf = (double*)p;
   p += 8 * 16;
+  L.ev = (double*)p;
+  p += 8 * 16;
+  L.perm = (int*)p;
+  p += 4 * 16;
   L.scal = (double*)p;
   p += 8 * 32;
   L.iscal = (int*)p;
@@ -108,7 +114,7 @@ __host__ __device__ inline int64_t batched_fixed_bytes(int k, int n_str, int n_l
   int64_t np = (int64_t)k * (k + 1) / 2, ns = tri(n_str);
   auto a16 = [](int64_t x) { return (x + 15) & ~int64_t(15); };
   int64_t b = a16(4 * n_str * np) + a16(4 * (int64_t)n_str * n_link) + a16(4 * n_str) +
-              a16(8 * n_str) + a16(8 * (2 * k * k + k)) + 8 * (3 * 256 + 32 + 32) + 4 * 16 + 16 +
+              a16(8 * n_str) + a16(8 * (2 * k * k + k)) + 8 * (3 * 256 + 48 + 32) + 8 * 16 + 16 +
               8 * 16 * 24 + 3 * a16(8 * ns);
   return b;
 }
@@ -199,7 +205,7 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
       for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int P = 16 * m + 4 * kq + r;
+          const int P = 16 * m + M::row(kq, r);
           if (P < NP) et[P * nbp + nt * 16 + col] = acc[m][r];
         }
     }
@@ -395,7 +401,7 @@ __device__ __forceinline__ void solve_one(const SolveArgs& A, int pos, char* lds
       const int nn = m + 1;
       if (tid < 256) L.Gs[tid] = L.G[tid];
       __syncthreads();
-      if (tid < 64) jacobi_lowest(L.Gs, L.Qv, nn, &L.scal[20], L.y);
+      if (tid < 64) jacobi_lowest(L.Gs, L.Qv, nn, &L.scal[20], L.y, L.ev, L.perm);
       __syncthreads();
       theta = L.scal[20];
     }
@@ -423,18 +429,11 @@ __device__ __forceinline__ void solve_one(const SolveArgs& A, int pos, char* lds
         if (j <= m) acc[j] += Vb[j * st + i] * t;
       L.tv[i] = t;
       X[i] = x;
-      if (restart) {
-        Vb[i] = x;
-        Sb[i] = sx;
-      }
     }
     block_sum<kMaxSpace + 3>(acc, L.red, L.scal);
     resid = sqrt(L.scal[kMaxSpace]);
     const double tt0 = L.scal[kMaxSpace + 1];
-    const double dx = L.scal[kMaxSpace + 2];
-    const int mb = restart ? 0 : m;
-    __syncthreads();
-    if (tid < kMaxSpace) L.cf[tid] = restart ? (tid == 0 ? dx : 0.0) : ((tid <= m) ? L.scal[tid] : 0.0);
+    if (tid < kMaxSpace) L.cf[tid] = (tid <= m) ? L.scal[tid] : 0.0;
     __syncthreads();
 
     const double tol = (phase == 32) ? A.r_tol_inner : A.r_tol;
@@ -461,10 +460,44 @@ __device__ __forceinline__ void solve_one(const SolveArgs& A, int pos, char* lds
       break;
     }
     if (iters >= A.max_iter) break;
+    int mb = m;
     if (restart) {
-      for (int i = tid; i < 256; i += blockDim.x) L.G[i] = 0.0;
+      // thick restart: keep the `keep` lowest Ritz vectors and their sigmas
+      const int keep = mmax / 2 < kKeep ? mmax / 2 : kKeep;
+      for (int64_t i = tid; i < ns; i += blockDim.x) {
+        double vv[kMaxSpace];
+#pragma unroll
+        for (int j = 0; j < kMaxSpace; ++j) vv[j] = (j <= m) ? Vb[j * st + i] : 0.0;
+        for (int kk = 0; kk < keep; ++kk) {
+          const int c = L.perm[kk];
+          double v = 0.0;
+#pragma unroll
+          for (int j = 0; j < kMaxSpace; ++j)
+            if (j <= m) v += L.Qv[j * 16 + c] * vv[j];
+          Vb[kk * st + i] = v;
+        }
+#pragma unroll
+        for (int j = 0; j < kMaxSpace; ++j) vv[j] = (j <= m) ? Sb[j * st + i] : 0.0;
+        for (int kk = 0; kk < keep; ++kk) {
+          const int c = L.perm[kk];
+          double v = 0.0;
+#pragma unroll
+          for (int j = 0; j < kMaxSpace; ++j)
+            if (j <= m) v += L.Qv[j * 16 + c] * vv[j];
+          Sb[kk * st + i] = v;
+        }
+      }
+      double cnew = 0.0;
+      if (tid < keep) {
+        const int c = L.perm[tid];
+        for (int j = 0; j <= m; ++j) cnew += L.Qv[j * 16 + c] * L.cf[j];
+      }
       __syncthreads();
-      if (tid == 0) L.G[0] = theta;
+      for (int i = tid; i < 256; i += blockDim.x) L.G[i] = 0.0;
+      if (tid < kMaxSpace) L.cf[tid] = (tid < keep) ? cnew : 0.0;
+      __syncthreads();
+      if (tid < keep) L.G[tid * 16 + tid] = L.ev[tid];
+      mb = keep - 1;
       __syncthreads();
     }
     // pass B: project out the basis (classical Gram-Schmidt), with a second

@@ -15,11 +15,14 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
 struct Mfma;
-// 16x16x4 tiles.  Lane L holds A[L % 16][L / 16], B[L / 16][L % 16] and the
-// accumulator rows 4 (L / 16) + r, column L % 16, r = 0..3.
+// 16x16x4 tiles.  Lane L holds A[L % 16][L / 16] and B[L / 16][L % 16];
+// accumulator register r of lane L holds column L % 16 and row row(L / 16, r):
+// 4 r + L / 16 for FP64 (v_mfma_f64_16x16x4f64), 4 (L / 16) + r for FP32
+// (v_mfma_f32_16x16x4f32), as measured on gfx950.
 template <>
 struct Mfma<double> {
   typedef d4 acc;
+  static __device__ __forceinline__ int row(int lane_hi, int r) { return 4 * r + lane_hi; }
   static __device__ __forceinline__ acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
   static __device__ __forceinline__ acc mma(double a, double b, acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -28,6 +31,7 @@ struct Mfma<double> {
 template <>
 struct Mfma<float> {
   typedef f4 acc;
+  static __device__ __forceinline__ int row(int lane_hi, int r) { return 4 * lane_hi + r; }
   static __device__ __forceinline__ acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
   static __device__ __forceinline__ acc mma(float a, float b, acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -80,11 +84,13 @@ __device__ __forceinline__ void lds_add(double* p, double v) {
 constexpr double kSqrt2 = 1.4142135623730950488;
 constexpr double kRSqrt2 = 0.70710678118654752440;
 
-// Lowest eigenpair of the symmetric n x n matrix A (row stride 16, n <= 16)
-// by cyclic Jacobi rotations (Golub & Van Loan, symmetric Schur
+// Eigen-decomposition of the symmetric n x n matrix A (row stride 16,
+// n <= 16) by cyclic Jacobi rotations (Golub & Van Loan, symmetric Schur
 // decomposition).  Executed by one full wavefront; A is overwritten, Q
-// (stride 16) receives the eigenvectors.  Lane i owns row i.
-__device__ inline void jacobi_lowest(double* A, double* Q, int n, double* theta, double* y) {
+// (stride 16) receives the eigenvectors, evals/perm the sorted eigenvalues
+// and their columns, theta/y the lowest pair.  Lane i owns row i.
+__device__ inline void jacobi_lowest(double* A, double* Q, int n, double* theta, double* y, double* evals,
+                                     int* perm) {
   const int lane = threadIdx.x & 63;
   if (lane < n)
     for (int j = 0; j < n; ++j) Q[lane * 16 + j] = (lane == j) ? 1.0 : 0.0;
@@ -134,14 +140,25 @@ __device__ inline void jacobi_lowest(double* A, double* Q, int n, double* theta,
     __builtin_amdgcn_wave_barrier();
   }
   __builtin_amdgcn_wave_barrier();
-  int imin = 0;
-  double best = A[0];
-  for (int i = 1; i < n; ++i) {
-    double v = A[i * 16 + i];
-    if (v < best) best = v, imin = i;
+  // eigenvalues in increasing order (ties by index): perm[i] is the column
+  // of Q holding the i-th lowest
+  if (lane == 0) {
+    for (int i = 0; i < n; ++i) perm[i] = i;
+    for (int i = 0; i < n; ++i) {
+      int b = i;
+      for (int j = i + 1; j < n; ++j) {
+        const double vj = A[perm[j] * 16 + perm[j]], vb = A[perm[b] * 16 + perm[b]];
+        if (vj < vb || (vj == vb && perm[j] < perm[b])) b = j;
+      }
+      const int t = perm[i];
+      perm[i] = perm[b];
+      perm[b] = t;
+      evals[i] = A[perm[i] * 16 + perm[i]];
+    }
+    *theta = evals[0];
   }
-  if (lane == 0) *theta = best;
-  if (lane < n) y[lane] = Q[lane * 16 + imin];
+  __builtin_amdgcn_wave_barrier();
+  if (lane < n) y[lane] = Q[lane * 16 + perm[0]];
   __builtin_amdgcn_wave_barrier();
 }
 

@@ -10,6 +10,7 @@ namespace ifci {
 
 constexpr int kMaxAct = 16;      // largest active space (orbitals)
 constexpr int kMaxSpace = 16;    // largest Davidson subspace
+constexpr int kKeep = 4;         // Ritz vectors kept at a thick restart
 constexpr int kBatchThreads = 512;
 
 // Device-side description of one increment.  Offsets count elements of the

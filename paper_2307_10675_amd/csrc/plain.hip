@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(kWideThreads) contract_kernel(IncDev d, const 
     if (m < MT) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int P = 16 * m + 4 * kq + r;
+        const int P = 16 * m + M::row(kq, r);
         if (P < NP && valid) E[(int64_t)P * ndet + j] = acc[m][r];
       }
     }
@@ -195,9 +195,11 @@ struct DavState {
   double y[16];
   double cf[16];
   double c2[16];
+  double ev[16];
   double theta, E0, resid, tt0, tt, dx, inv, ecore;
   int m, phase, iters, status, restart, action, mb, reorth;
-  int guess, pad[7];
+  int guess, keep, pad[6];
+  int perm[16];
 };
 
 constexpr int kPartBlocks = 1024;
@@ -304,6 +306,7 @@ __global__ void init_state_kernel(DavState* S, const double* part, int nblk, dou
     S->status = IFCI_INC_NOT_CONVERGED;
     S->action = 0;
     S->ecore = ecore;
+    S->keep = 0;
     S->theta = 0.0;
     S->resid = 1e300;
   }
@@ -339,9 +342,10 @@ __global__ void __launch_bounds__(64) small_G_kernel(DavState* S, const double* 
   __syncthreads();
   for (int i = threadIdx.x; i < 256; i += 64) S->Gs[i] = S->G[i];
   __syncthreads();
-  jacobi_lowest(S->Gs, S->Q, m + 1, &S->theta, S->y);
+  jacobi_lowest(S->Gs, S->Q, m + 1, &S->theta, S->y, S->ev, S->perm);
   if (threadIdx.x == 0) {
     S->restart = (m + 1 == mmax);
+    S->keep = mmax / 2 < kKeep ? mmax / 2 : kKeep;
     S->iters += 1;
   }
 }
@@ -354,7 +358,6 @@ __global__ void __launch_bounds__(256) passA_kernel(const DavState* __restrict__
   __shared__ double y[16];
   const int m = S->m;
   const double theta = S->theta, E0 = S->E0;
-  const bool restart = S->restart != 0;
   if (threadIdx.x < 16) y[threadIdx.x] = S->y[threadIdx.x];
   __syncthreads();
   double acc[kNV];
@@ -378,10 +381,6 @@ __global__ void __launch_bounds__(256) passA_kernel(const DavState* __restrict__
       if (j <= m) acc[j] += Vb[j * st + i] * t;
     T[i] = t;
     X[i] = x;
-    if (restart) {
-      Vb[i] = x;
-      Sb[i] = sx;
-    }
   }
   // pack: dots in [0, m], then rr, tt0, dx at m+1..m+3
   double out[kNV];
@@ -411,9 +410,8 @@ __global__ void __launch_bounds__(64) small_A_kernel(DavState* S, const double* 
     S->resid = sqrt(rr);
     S->tt0 = v[m + 2];
     S->dx = v[m + 3];
-    const bool restart = S->restart != 0;
-    for (int j = 0; j < 16; ++j) S->cf[j] = restart ? (j == 0 ? S->dx : 0.0) : ((j <= m) ? v[j] : 0.0);
-    S->mb = restart ? 0 : m;
+    for (int j = 0; j < 16; ++j) S->cf[j] = (j <= m) ? v[j] : 0.0;
+    S->mb = m;
     const double tol = S->phase == 32 ? tol32 : tol64;
     int action = 0;
     if (evict) {
@@ -430,11 +428,52 @@ __global__ void __launch_bounds__(64) small_A_kernel(DavState* S, const double* 
       action = 3;
     }
     S->action = action;
-    if (action == 0 && restart) {
-      for (int i = 0; i < 256; ++i) S->G[i] = 0.0;
-      S->G[0] = S->theta;
+  }
+}
+
+// Thick restart, device-wide: V[k] <- sum_j Q[j][perm k] V[j] for the keep
+// lowest Ritz vectors, same for S.
+__global__ void __launch_bounds__(256) restart_kernel(const DavState* __restrict__ S, double* Vb, double* Sb,
+                                                      int64_t st, int64_t ns) {
+  __shared__ double q[kMaxSpace * kKeep];
+  const int m = S->m, keep = S->keep;
+  for (int t = threadIdx.x; t < kMaxSpace * kKeep; t += blockDim.x) {
+    const int j = t / kKeep, kk = t % kKeep;
+    q[t] = (j <= m && kk < keep) ? S->Q[j * 16 + S->perm[kk]] : 0.0;
+  }
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int pass = 0; pass < 2; ++pass) {
+      double* B = pass == 0 ? Vb : Sb;
+      double vv[kMaxSpace];
+#pragma unroll
+      for (int j = 0; j < kMaxSpace; ++j) vv[j] = (j <= m) ? B[j * st + i] : 0.0;
+#pragma unroll
+      for (int kk = 0; kk < kKeep; ++kk) {
+        if (kk < keep) {
+          double v = 0.0;
+#pragma unroll
+          for (int j = 0; j < kMaxSpace; ++j) v += q[j * kKeep + kk] * vv[j];
+          B[kk * st + i] = v;
+        }
+      }
     }
   }
+}
+
+__global__ void small_R_kernel(DavState* S) {
+  if (threadIdx.x != 0) return;
+  const int m = S->m, keep = S->keep;
+  double cn[kKeep];
+  for (int kk = 0; kk < keep; ++kk) {
+    double c = 0.0;
+    for (int j = 0; j <= m; ++j) c += S->Q[j * 16 + S->perm[kk]] * S->cf[j];
+    cn[kk] = c;
+  }
+  for (int j = 0; j < 16; ++j) S->cf[j] = j < keep ? cn[j] : 0.0;
+  for (int i = 0; i < 256; ++i) S->G[i] = 0.0;
+  for (int kk = 0; kk < keep; ++kk) S->G[kk * 16 + kk] = S->ev[kk];
+  S->mb = keep - 1;
 }
 
 __global__ void __launch_bounds__(256) switch_kernel(DavState* S, double* Vb, const double* X, int64_t ns) {
@@ -599,6 +638,12 @@ hipError_t run_plain(const PlainArgs& A, double* e_out, int32_t* status_out, int
       m = 0;
       phase = 64;
       continue;
+    }
+    if (hs.restart) {
+      hipLaunchKernelGGL(restart_kernel, dim3(nb), dim3(256), 0, st, S, Vb, Sb, sd, ns);
+      hipLaunchKernelGGL(small_R_kernel, dim3(1), dim3(64), 0, st, S);
+      if ((e = hipMemcpyAsync(&hs, S, sizeof(DavState), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+      if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(passB_kernel, dim3(nb), dim3(256), 0, st, S, Vb, sd, T, ns, A.part);
     hipLaunchKernelGGL(small_B_kernel, dim3(1), dim3(64), 0, st, S, A.part, (int)nb);

@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(kRdmThreads) rdm_kernel(const IncDev* __restri
       const int tx = tile / nt, ty = tile % nt;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int x = tx * 16 + 4 * (lane >> 4) + r, y = ty * 16 + (lane & 15);
+        const int x = tx * 16 + Mfma<double>::row(lane >> 4, r), y = ty * 16 + (lane & 15);
         if (x < k2 && y < k2) {
           // x = (q, p) of E_qp, y = (r, s): Gamma'_pqrs = M[(q,p)][(r,s)]
           const int q = x / k, p = x % k;
