@@ -106,7 +106,7 @@ typedef struct {
 int ifci_abi_version(void);
 
 /* Fill *opt with the defaults: FP64, batched, r_tol 1e-7, r_tol_inner 1e-4,
- * max_iter 100, max_space 12. */
+ * max_iter 300, max_space 12. */
 void ifci_default_options(ifci_options* opt);
 
 /* Validate the problem, enumerate the increments, build the string and

@@ -148,7 +148,7 @@ void ifci_default_options(ifci_options* o) {
   o->solver = IFCI_SOLVER_BATCHED;
   o->r_tol = 1e-7;
   o->r_tol_inner = 1e-4;
-  o->max_iter = 100;
+  o->max_iter = 300;
   o->max_space = 12;
   o->flags = 0;
 }

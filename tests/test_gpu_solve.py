@@ -80,9 +80,9 @@ def test_workload2_sample_fp64_and_mixed():
     g = load_golden("w2_sample")
     _check_sha(p, g)
     print("[solve] workload 2 fp64", flush=True)
-    plan64, r64 = ifci.solve(p, r_tol=1e-8)
+    plan64, r64 = ifci.solve(p, r_tol=1e-7, max_iter=300)
     print("[solve] workload 2 mixed", flush=True)
-    plan32, r32 = ifci.solve(p, precision=ifci.MIXED, r_tol=3e-5, r_tol_inner=1e-5)
+    plan32, r32 = ifci.solve(p, precision=ifci.MIXED, r_tol=3e-5, r_tol_inner=1e-5, max_iter=300)
     torch.cuda.synchronize()
     incs = [i.bodies for i in plan64.increments()]
     E64 = r64["E"].cpu().numpy()
