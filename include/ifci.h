@@ -197,6 +197,14 @@ ifci_status ifci_energy(ifci_plan_t plan, const double* e_inc, const int32_t* st
 ifci_status ifci_rdm(ifci_plan_t plan, const double* weights, double* dE_dh, double* dE_deri,
                      ifci_stream_t stream);
 
+/* Tracing: when `counters` (device [n_inc][8] int64, or NULL to switch off)
+ * is set, the batched solver adds per increment the shader-clock cycles of
+ * its phases: 0 set-up and diagonal, 1 sigma, 2 subspace matrix and
+ * eigensolve, 3 residual and preconditioning, 4 thick restart, 5
+ * orthogonalisation, and writes 6 the sigma count and 7 the total cycles.
+ * The caller zeroes the buffer; it must outlive the next ifci_davidson. */
+ifci_status ifci_set_phase_counters(ifci_plan_t plan, int64_t* counters, int64_t n);
+
 const char* ifci_status_string(ifci_status s);
 const char* ifci_last_error(void);
 

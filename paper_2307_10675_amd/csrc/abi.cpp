@@ -122,15 +122,13 @@ ifci_status need_ints(ifci_plan_t p) {
   return IFCI_OK;
 }
 
-// LDS the batched solver asks for when running increments `ids`.
+// LDS the batched solver asks for when running increments `ids`: enough
+// for every wave's FP64 E slice, capped at the hardware limit.
 int batch_lds(const ifci_plan_s* P, const std::vector<int32_t>& ids) {
   int64_t need = 0;
   for (int32_t i : ids) {
     const IncDev& d = P->inc[i];
-    // fixed part plus E slices for every wave, capped at the hardware limit
-    int64_t np = (int64_t)d.npair, nbp = ((int64_t)d.n_str + 15) / 16 * 16;
-    int64_t want = batched_lds_bytes(d.k, d.n_str, d.n_link) + (kBatchThreads / 64 - 1) * ((np * nbp * 8 + 15) & ~15);
-    need = std::max(need, want);
+    need = std::max(need, batched_lds_want(d.k, d.n_str, d.n_link));
   }
   return (int)std::min<int64_t>(kMaxLds, (need + 255) & ~int64_t(255));
 }
@@ -422,6 +420,7 @@ ifci_status ifci_davidson(ifci_plan_t p, int64_t first, int64_t count, double* e
     A.resid_out = resid_out;
     A.evict = evict_mask;
     A.e_const = p->e_const;
+    A.phase = p->phase_counters;
     HIP_TRY(launch_batched(A, batch_lds(p, ids), st), "ifci_davidson batched");
   }
   if (!rest.empty()) {
@@ -458,6 +457,16 @@ ifci_status ifci_davidson(ifci_plan_t p, int64_t first, int64_t count, double* e
     }
   }
   for (int64_t i = first; i < first + count; ++i) p->solved[i] = 1;
+  return IFCI_OK;
+}
+
+ifci_status ifci_set_phase_counters(ifci_plan_t p, int64_t* counters, int64_t n) {
+  if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
+  if (counters && n < (int64_t)p->inc.size() * kPhases) {
+    set_error("ifci_set_phase_counters: need n_inc * 8 counters");
+    return IFCI_ERR_ARG;
+  }
+  p->phase_counters = counters;
   return IFCI_OK;
 }
 

@@ -23,60 +23,97 @@
 // Vectors are stored packed and scaled: entry (a <= b) holds C[a][b] times
 // sqrt(2) when a != b, so that plain dot products of packed vectors equal
 // full-space dot products.
+//
+// LDS holds a persistent part (tables, subspace matrix and its eigenvectors,
+// the CI vector and the sigma accumulator) and a transient part (working
+// vector, eigensolver scratch, reduction buffers) that the per-wave E slices
+// overlay while sigma runs.
 #include "device_common.hpp"
 #include "launch.hpp"
 
 namespace ifci {
 
 struct Lds {
-  int32_t* ptab;   // [n_str][np]
-  int32_t* links;  // [n_str][n_link]
+  // persistent
+  int32_t* ptab;   // [n_str][np] decoded pair table: J | neg << 16, J = n_str if no link
+  int32_t* links;  // [n_str][n_link]  (Q << 17 | J << 1 | neg)
   int32_t* strs;   // [n_str]
-  double* F;       // [n_str]
-  double* Jm;      // [k*k]
-  double* Km;      // [k*k]
-  double* hd;      // [k]
+  double* F;       // [n_str] string energies
+  double* Jm;      // [k*k] (pp|qq)
+  double* Km;      // [k*k] (pq|qp)
+  double* hd;      // [k] h'_pp
   double* G;       // [16*16] subspace matrix
-  double* Gs;      // [16*16] copy diagonalised
-  double* Qv;      // [16*16] eigenvectors
+  double* Qp;      // [16*16] eigenvectors of the previous subspace matrix
+  double* Lam;     // [16] its eigenvalues
+  double* cp;      // CI vector: FP64 packed [n_sym]; FP32 full [(n+1)^2] with a zero
+                   // last row and column
+  double* sp;      // [n_sym] sigma accumulator, packed scaled
+  // transient (overlaid by the E slices during sigma)
+  double* tv;      // [n_sym] working vector, packed scaled
+  double* Gs;      // [16*16]
+  double* Qv;      // [16*16]
   double* y;       // [16]
   double* cf;      // [16] projection coefficients
-  double* ev;      // [16] sorted subspace eigenvalues
-  int* perm;       // [16] their eigenvector columns
+  double* ev;      // [16] sorted eigenvalues
+  int* perm;       // [16]
   double* scal;    // [32]
   int* iscal;      // [16]
   double* red;     // [16 waves * 24]
-  double* cp;      // [n_sym] CI vector, packed unscaled (type T)
-  double* sp;      // [n_sym] sigma accumulator, packed scaled
-  double* tv;      // [n_sym] working vector, packed scaled
-  char* et;        // per-wave E column slices
-  int et_total;    // bytes available for the slices
+  char* et;        // E slices (start of the transient part)
+  int et_total;    // bytes from et to the end of LDS
 };
 
-__device__ __forceinline__ char* align16(char* p) {
-  return (char*)(((uintptr_t)p + 15) & ~(uintptr_t)15);
+__host__ __device__ inline int64_t a16(int64_t x) { return (x + 15) & ~int64_t(15); }
+
+__host__ __device__ inline int64_t cp_bytes(int n_str) {
+  const int64_t a = 8 * tri(n_str), b = 4 * (int64_t)(n_str + 1) * (n_str + 1);
+  return a16(a > b ? a : b);
+}
+__host__ __device__ inline int64_t persistent_bytes(int k, int n_str, int n_link) {
+  const int64_t np = (int64_t)k * (k + 1) / 2, ns = tri(n_str);
+  return a16(4 * n_str * np) + a16(4 * (int64_t)n_str * n_link) + a16(4 * n_str) + a16(8 * n_str) +
+         a16(8 * (2 * k * k + k)) + 8 * (256 + 256 + 16) + cp_bytes(n_str) + a16(8 * ns);
+}
+__host__ __device__ inline int64_t transient_bytes(int n_str) {
+  return a16(8 * tri(n_str)) + 8 * (256 + 256 + 16 + 16 + 16) + 4 * 16 + 8 * 32 + 4 * 16 + 16 + 8 * 16 * 24;
+}
+__host__ __device__ inline int64_t et_slice_bytes(int k, int n_str, int elem) {
+  const int64_t np = (int64_t)k * (k + 1) / 2;
+  const int64_t nbp = ((int64_t)n_str + 15) / 16 * 16;
+  return a16(np * nbp * elem);
 }
 
-__device__ inline Lds carve(char* base, const IncDev& d, int lds_bytes, int et_waves) {
+__device__ inline Lds carve(char* base, const IncDev& d, int lds_bytes) {
   Lds L;
   char* p = base;
   const int n = d.n_str, np = d.npair, k = d.k;
   L.ptab = (int32_t*)p;
-  p = align16(p + 4 * n * np);
+  p += a16(4 * n * np);
   L.links = (int32_t*)p;
-  p = align16(p + 4 * n * d.n_link);
+  p += a16(4 * n * d.n_link);
   L.strs = (int32_t*)p;
-  p = align16(p + 4 * n);
+  p += a16(4 * n);
   L.F = (double*)p;
-  p = align16(p + 8 * n);
+  p += a16(8 * n);
   L.Jm = (double*)p;
-  p += 8 * k * k;
-  L.Km = (double*)p;
-  p += 8 * k * k;
-  L.hd = (double*)p;
-  p = align16(p + 8 * k);
+  L.Km = L.Jm + k * k;
+  L.hd = L.Km + k * k;
+  p += a16(8 * (2 * k * k + k));
   L.G = (double*)p;
   p += 8 * 256;
+  L.Qp = (double*)p;
+  p += 8 * 256;
+  L.Lam = (double*)p;
+  p += 8 * 16;
+  L.cp = (double*)p;
+  p += cp_bytes(n);
+  L.sp = (double*)p;
+  p += a16(8 * d.n_sym);
+  // transient
+  L.et = p;
+  L.et_total = (int)((base + lds_bytes) - p);
+  L.tv = (double*)p;
+  p += a16(8 * d.n_sym);
   L.Gs = (double*)p;
   p += 8 * 256;
   L.Qv = (double*)p;
@@ -93,35 +130,14 @@ __device__ inline Lds carve(char* base, const IncDev& d, int lds_bytes, int et_w
   p += 8 * 32;
   L.iscal = (int*)p;
   p += 4 * 16;
-  p = align16(p);
+  p = (char*)(((uintptr_t)p + 15) & ~(uintptr_t)15);
   L.red = (double*)p;
-  p += 8 * 16 * 24;
-  L.cp = (double*)p;
-  p = align16(p + 8 * d.n_sym);
-  L.sp = (double*)p;
-  p = align16(p + 8 * d.n_sym);
-  L.tv = (double*)p;
-  p = align16(p + 8 * d.n_sym);
-  L.et = p;
-  L.et_total = (int)((base + lds_bytes) - p);
-  (void)et_waves;
   return L;
 }
 
-// Bytes of LDS the batched solver needs for an increment, excluding the E
-// slices, and the bytes of one wave's E slice in precision T.
-__host__ __device__ inline int64_t batched_fixed_bytes(int k, int n_str, int n_link) {
-  int64_t np = (int64_t)k * (k + 1) / 2, ns = tri(n_str);
-  auto a16 = [](int64_t x) { return (x + 15) & ~int64_t(15); };
-  int64_t b = a16(4 * n_str * np) + a16(4 * (int64_t)n_str * n_link) + a16(4 * n_str) +
-              a16(8 * n_str) + a16(8 * (2 * k * k + k)) + 8 * (3 * 256 + 48 + 32) + 8 * 16 + 16 +
-              8 * 16 * 24 + 3 * a16(8 * ns);
-  return b;
-}
-__host__ __device__ inline int64_t et_slice_bytes(int k, int n_str, int elem) {
-  int64_t np = (int64_t)k * (k + 1) / 2;
-  int64_t nbp = ((int64_t)n_str + 15) / 16 * 16;
-  return (np * nbp * elem + 15) & ~int64_t(15);
+// 32-bit packed index of (x, y) in the upper triangle (at most 70 strings here).
+__device__ __forceinline__ int pk32(int x, int y) {
+  return x <= y ? ((y * (y + 1)) >> 1) + x : ((x * (x + 1)) >> 1) + y;
 }
 
 // ---------------------------------------------------------------------------
@@ -132,7 +148,7 @@ __host__ __device__ inline int64_t et_slice_bytes(int k, int n_str, int elem) {
 // = shift from the operator.
 template <typename T, int K>
 __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, const double* __restrict__ V,
-                             double shift, int et_waves) {
+                                             double shift, int et_waves) {
   constexpr int NP = K * (K + 1) / 2;
   constexpr int MT = (NP + 15) / 16;
   constexpr int KS = (NP + 3) / 4;
@@ -167,37 +183,48 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
       }
   }
   if (wave >= et_waves) return;
-  T* et = (T*)(L.et + (size_t)wave * et_slice_bytes(K, n, (int)sizeof(T)));
   const int nt_count = (n + 15) / 16;
   const int nbp = nt_count * 16;
+  T* et = (T*)(L.et + (size_t)wave * et_slice_bytes(K, n, (int)sizeof(T)));
   const int kq = lane >> 4, col = lane & 15;
+  constexpr bool kFull = sizeof(T) == 4;  // FP32: full (n+1)^2 layout, FP64: packed
+  const int ld = n + 1;
 
   for (int b = wave; b < n; b += et_waves) {
-    const int32_t* tb = L.ptab + b * NP;
+    // beta-part entries of column b, one per k-step of this lane
+    int jb[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int Q = 4 * s + kq;
+      jb[s] = (Q < NP) ? L.ptab[b * NP + Q] : n;
+    }
     for (int nt = 0; nt < nt_count; ++nt) {
       const int a = nt * 16 + col;
-      const bool valid = a < n;
+      const int ac = a < n ? a : n;  // a padding row reads zeros (full layout)
       typename M::acc acc[MT];
 #pragma unroll
       for (int m = 0; m < MT; ++m) acc[m] = M::zero();
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
+        // D[Q][(a,b)] = sign1 c[J1][b] + sign2 c[a][J2]; a missing link has
+        // J = n, which addresses the zero row / column (full layout)
         const int Q = 4 * s + kq;
-        T bv = (T)0;
-        if (valid && Q < NP) {
-          const int e1 = L.ptab[a * NP + Q];
-          if (e1 >= 0) {
-            const int J = e1 >> 1;
-            const T v = cp[packed(J, b)];
-            bv = (e1 & 1) ? -v : v;
-          }
-          const int e2 = tb[Q];
-          if (e2 >= 0) {
-            const int J = e2 >> 1;
-            const T v = cp[packed(a, J)];
-            bv += (e2 & 1) ? -v : v;
-          }
+        const int e1 = (a < n && Q < NP) ? L.ptab[a * NP + Q] : n;
+        const int e2 = jb[s];
+        T v1, v2;
+        if (kFull) {
+          v1 = cp[(e1 & 0xFFFF) * ld + b];
+          v2 = cp[ac * ld + (e2 & 0xFFFF)];
+        } else {
+          // packed layout: clamp to a valid entry, then zero the missing links
+          const int J1 = e1 & 0xFFFF, J2 = e2 & 0xFFFF;
+          const int a0 = a < n ? a : 0;
+          v1 = cp[pk32(J1 < n ? J1 : 0, b)];
+          v2 = cp[pk32(a0, J2 < n ? J2 : 0)];
+          v1 = (J1 < n) ? v1 : (T)0;
+          v2 = (J2 < n && a < n) ? v2 : (T)0;
         }
+        const T bv = ((e1 >> 16) ? -v1 : v1) + ((e2 >> 16) ? -v2 : v2);
 #pragma unroll
         for (int m = 0; m < MT; ++m) acc[m] = M::mma(afr[m][s], bv, acc[m]);
       }
@@ -222,7 +249,7 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
         s += (code & 1) ? -v : v;
       }
       const double sc = (a == b) ? 2.0 : kSqrt2;
-      lds_add(&L.sp[packed(a, b)], sc * (double)s);
+      lds_add(&L.sp[pk32(a, b)], sc * (double)s);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -230,17 +257,42 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
   }
 }
 
+// Pair table (decoded: J | neg << 16, J = n_str for no link) and link lists into LDS.
+__device__ inline void load_tables(const IncDev& d, const Lds& L, const int32_t* __restrict__ tables) {
+  const int n = d.n_str, np = d.npair;
+  for (int i = threadIdx.x; i < n * np; i += blockDim.x) {
+    const int e = tables[d.pair_off + i];
+    L.ptab[i] = e < 0 ? n : ((e >> 1) | ((e & 1) << 16));
+  }
+  for (int i = threadIdx.x; i < n * d.n_link; i += blockDim.x) L.links[i] = tables[d.link_off + i];
+}
+
 // Expand the packed scaled vector tv into the packed unscaled cp of type T
 // and clear sp.
 template <typename T>
 __device__ inline void prepare_sigma(const IncDev& d, const Lds& L) {
   T* cp = (T*)L.cp;
-  for (int64_t i = threadIdx.x; i < d.n_sym; i += blockDim.x) {
-    int a, b;
-    unpack(i, &a, &b);
-    const double v = L.tv[i];
-    cp[i] = (T)(a == b ? v : v * kRSqrt2);
-    L.sp[i] = 0.0;
+  const int n = d.n_str, ld = n + 1;
+  if (sizeof(T) == 4) {
+    // full symmetric matrix with a zero last row and column
+    for (int i = threadIdx.x; i < ld * ld; i += blockDim.x) {
+      const int a = i / ld, b = i - a * ld;
+      double v = 0.0;
+      if (a < n && b < n) {
+        v = L.tv[pk32(a, b)];
+        if (a != b) v *= kRSqrt2;
+      }
+      cp[i] = (T)v;
+    }
+    for (int64_t i = threadIdx.x; i < d.n_sym; i += blockDim.x) L.sp[i] = 0.0;
+  } else {
+    for (int64_t i = threadIdx.x; i < d.n_sym; i += blockDim.x) {
+      int a, b;
+      unpack(i, &a, &b);
+      const double v = L.tv[i];
+      cp[i] = (T)(a == b ? v : v * kRSqrt2);
+      L.sp[i] = 0.0;
+    }
   }
   __syncthreads();
 }
@@ -261,14 +313,12 @@ __device__ inline int et_waves_for(const IncDev& d, const Lds& L) {
   return w > nw ? nw : w;
 }
 
-// Load the increment's tables and diagonal data; returns the index of the
-// lowest diagonal element (packed) and writes the diagonal to HD.
+// Load the increment's tables and diagonal data and write the diagonal to HD.
 __device__ inline void load_increment(const IncDev& d, const Lds& L, const int32_t* __restrict__ tables,
                                       const double* __restrict__ B, double* __restrict__ HD) {
   const int n = d.n_str, np = d.npair, k = d.k;
   const IntBlock ib = int_block(k);
-  for (int i = threadIdx.x; i < n * np; i += blockDim.x) L.ptab[i] = tables[d.pair_off + i];
-  for (int i = threadIdx.x; i < n * d.n_link; i += blockDim.x) L.links[i] = tables[d.link_off + i];
+  load_tables(d, L, tables);
   for (int i = threadIdx.x; i < n; i += blockDim.x) L.strs[i] = tables[d.str_off + i];
   for (int i = threadIdx.x; i < k * k; i += blockDim.x) {
     L.Jm[i] = B[ib.J + i];
@@ -335,12 +385,50 @@ __device__ inline void argmin_block(const double* __restrict__ HD, int64_t ns, c
   __syncthreads();
 }
 
+// Subspace eigenproblem of the (m+1)-dimensional matrix G, warm started:
+// with the previous block's eigenpairs (Lam, Qp), G is first rotated to
+// [[diag(Lam), Qp^T g], [., g_mm]] (g = the new column), and Jacobi only
+// has to resolve that arrowhead.  Leaves Lam/Qp for the next call, the
+// sorted eigenvalues in ev/perm and the lowest pair in scal[20] / y.
+__device__ inline void subspace_solve(const Lds& L, int m) {
+  const int tid = threadIdx.x, n = m + 1;
+  if (tid < 256) {
+    const int i = tid >> 4, j = tid & 15;
+    double gs = 0.0, q = 0.0;
+    if (i < n && j < n) {
+      if (i < m && j < m) {
+        gs = (i == j) ? L.Lam[i] : 0.0;
+        q = L.Qp[i * 16 + j];
+      } else if (i == m && j == m) {
+        gs = L.G[m * 16 + m];
+        q = 1.0;
+      } else {
+        const int r = (i == m) ? j : i;  // entry r of Qp^T g
+        double s = 0.0;
+        for (int l = 0; l < m; ++l) s += L.Qp[l * 16 + r] * L.G[l * 16 + m];
+        gs = s;
+        q = 0.0;
+      }
+    }
+    L.Gs[tid] = gs;
+    L.Qv[tid] = q;
+  }
+  __syncthreads();
+  if (tid < 64) jacobi_warm(L.Gs, L.Qv, n, &L.scal[20], L.y, L.ev, L.perm);
+  __syncthreads();
+  if (tid < 256) {
+    const int i = tid >> 4;
+    L.Qp[tid] = L.Qv[tid];
+    if ((tid & 15) == 0 && i < n) L.Lam[i] = L.Gs[i * 16 + i];
+  }
+  __syncthreads();
+}
+
 template <int K>
 __device__ __forceinline__ void solve_one(const SolveArgs& A, int pos, char* lds, int lds_bytes) {
   const int id = A.order[pos];
   const IncDev d = A.inc[id];
-  const int nw = blockDim.x >> 6;
-  Lds L = carve(lds, d, lds_bytes, nw);
+  Lds L = carve(lds, d, lds_bytes);
   const double* B = A.ints + d.int_off;
   const IntBlock ib = int_block(d.k);
   const double* Vm = B + ib.V;
@@ -352,6 +440,17 @@ __device__ __forceinline__ void solve_one(const SolveArgs& A, int pos, char* lds
   double* HD = base + 2 * mmax * st; // [stride]
   double* X = HD + st;               // [stride]
   const int tid = threadIdx.x;
+  int64_t ph[kPhases];
+#pragma unroll
+  for (int q = 0; q < kPhases; ++q) ph[q] = 0;
+  const bool trace = A.phase != nullptr;
+  int64_t t_start = trace ? clock64() : 0, t_mark = t_start;
+#define IFCI_MARK(PH)                      \
+  if (trace) {                             \
+    const int64_t now_ = clock64();        \
+    ph[PH] += now_ - t_mark;               \
+    t_mark = now_;                         \
+  }
 
   load_increment(d, L, A.tables, B, HD);
   argmin_block(HD, ns, L);
@@ -364,6 +463,7 @@ __device__ __forceinline__ void solve_one(const SolveArgs& A, int pos, char* lds
   }
   for (int i = tid; i < 256; i += blockDim.x) L.G[i] = 0.0;
   __syncthreads();
+  IFCI_MARK(kPhPrologue);
 
   const int ew64 = et_waves_for<double, K>(d, L);
   const int ew32 = et_waves_for<float, K>(d, L);
@@ -372,6 +472,7 @@ __device__ __forceinline__ void solve_one(const SolveArgs& A, int pos, char* lds
   double theta = 0.0, resid = 1e300;
   const int64_t o = (int64_t)id - A.first;  // position in the caller's range
   const bool evict = A.evict && A.evict[o] != 0;
+  const int keep = mmax / 2 < kKeep ? mmax / 2 : kKeep;
 
   while (true) {
     // sigma of the newest basis vector (in L.tv) -> S[m]
@@ -381,7 +482,8 @@ __device__ __forceinline__ void solve_one(const SolveArgs& A, int pos, char* lds
       sigma_phase<double, K>(d, L, Vm, E0, ew64);
     ++iters;
     for (int64_t i = tid; i < ns; i += blockDim.x) Sb[m * st + i] = L.sp[i];
-    // new column of the subspace matrix
+    IFCI_MARK(kPhSigma);
+    // new column of the subspace matrix, then its eigenpairs
     {
       double g[kMaxSpace];
 #pragma unroll
@@ -398,43 +500,50 @@ __device__ __forceinline__ void solve_one(const SolveArgs& A, int pos, char* lds
         L.G[m * 16 + tid] = L.scal[tid];
       }
       __syncthreads();
-      const int nn = m + 1;
-      if (tid < 256) L.Gs[tid] = L.G[tid];
-      __syncthreads();
-      if (tid < 64) jacobi_lowest(L.Gs, L.Qv, nn, &L.scal[20], L.y, L.ev, L.perm);
-      __syncthreads();
+      subspace_solve(L, m);
       theta = L.scal[20];
     }
+    IFCI_MARK(kPhSubspace);
     const bool restart = (m + 1 == mmax);
     // pass A: Ritz vector x, its sigma, residual, preconditioned correction
-    double acc[kMaxSpace + 3];
+    double acc[kMaxSpace + 2];
 #pragma unroll
-    for (int j = 0; j < kMaxSpace + 3; ++j) acc[j] = 0.0;
-    for (int64_t i = tid; i < ns; i += blockDim.x) {
-      double x = 0.0, sx = 0.0;
-      for (int j = 0; j <= m; ++j) {
-        const double yj = L.y[j];
-        x += yj * Vb[j * st + i];
-        sx += yj * Sb[j * st + i];
+    for (int j = 0; j < kMaxSpace + 2; ++j) acc[j] = 0.0;
+    {
+      double yy[kMaxSpace];
+#pragma unroll
+      for (int j = 0; j < kMaxSpace; ++j) yy[j] = (j <= m) ? L.y[j] : 0.0;
+      for (int64_t i = tid; i < ns; i += blockDim.x) {
+        double vv[kMaxSpace];
+        double x = 0.0, sx = 0.0;
+#pragma unroll
+        for (int j = 0; j < kMaxSpace; ++j) {
+          if (j <= m) {
+            vv[j] = Vb[j * st + i];
+            x += yy[j] * vv[j];
+            sx += yy[j] * Sb[j * st + i];
+          } else {
+            vv[j] = 0.0;
+          }
+        }
+        const double r = sx - theta * x;
+        double den = theta - (HD[i] - E0);
+        if (fabs(den) < 1e-8) den = (den < 0.0) ? -1e-8 : 1e-8;
+        const double t = r / den;
+        acc[kMaxSpace] += r * r;
+        acc[kMaxSpace + 1] += t * t;
+#pragma unroll
+        for (int j = 0; j < kMaxSpace; ++j) acc[j] += vv[j] * t;
+        L.tv[i] = t;
+        X[i] = x;
       }
-      const double r = sx - theta * x;
-      double den = theta - (HD[i] - E0);
-      if (fabs(den) < 1e-8) den = (den < 0.0) ? -1e-8 : 1e-8;
-      const double t = r / den;
-      acc[kMaxSpace] += r * r;
-      acc[kMaxSpace + 1] += t * t;
-      acc[kMaxSpace + 2] += x * t;
-#pragma unroll
-      for (int j = 0; j < kMaxSpace; ++j)
-        if (j <= m) acc[j] += Vb[j * st + i] * t;
-      L.tv[i] = t;
-      X[i] = x;
     }
-    block_sum<kMaxSpace + 3>(acc, L.red, L.scal);
+    block_sum<kMaxSpace + 2>(acc, L.red, L.scal);
     resid = sqrt(L.scal[kMaxSpace]);
     const double tt0 = L.scal[kMaxSpace + 1];
     if (tid < kMaxSpace) L.cf[tid] = (tid <= m) ? L.scal[tid] : 0.0;
     __syncthreads();
+    IFCI_MARK(kPhPassA);
 
     const double tol = (phase == 32) ? A.r_tol_inner : A.r_tol;
     if (evict) {
@@ -463,7 +572,6 @@ __device__ __forceinline__ void solve_one(const SolveArgs& A, int pos, char* lds
     int mb = m;
     if (restart) {
       // thick restart: keep the `keep` lowest Ritz vectors and their sigmas
-      const int keep = mmax / 2 < kKeep ? mmax / 2 : kKeep;
       for (int64_t i = tid; i < ns; i += blockDim.x) {
         double vv[kMaxSpace];
 #pragma unroll
@@ -473,7 +581,7 @@ __device__ __forceinline__ void solve_one(const SolveArgs& A, int pos, char* lds
           double v = 0.0;
 #pragma unroll
           for (int j = 0; j < kMaxSpace; ++j)
-            if (j <= m) v += L.Qv[j * 16 + c] * vv[j];
+            if (j <= m) v += L.Qp[j * 16 + c] * vv[j];
           Vb[kk * st + i] = v;
         }
 #pragma unroll
@@ -483,36 +591,53 @@ __device__ __forceinline__ void solve_one(const SolveArgs& A, int pos, char* lds
           double v = 0.0;
 #pragma unroll
           for (int j = 0; j < kMaxSpace; ++j)
-            if (j <= m) v += L.Qv[j * 16 + c] * vv[j];
+            if (j <= m) v += L.Qp[j * 16 + c] * vv[j];
           Sb[kk * st + i] = v;
         }
       }
       double cnew = 0.0;
       if (tid < keep) {
         const int c = L.perm[tid];
-        for (int j = 0; j <= m; ++j) cnew += L.Qv[j * 16 + c] * L.cf[j];
+        for (int j = 0; j <= m; ++j) cnew += L.Qp[j * 16 + c] * L.cf[j];
       }
       __syncthreads();
-      for (int i = tid; i < 256; i += blockDim.x) L.G[i] = 0.0;
+      // the kept Ritz vectors diagonalise the new subspace matrix
+      for (int i = tid; i < 256; i += blockDim.x) {
+        L.G[i] = 0.0;
+        L.Qp[i] = ((i >> 4) == (i & 15)) ? 1.0 : 0.0;
+      }
       if (tid < kMaxSpace) L.cf[tid] = (tid < keep) ? cnew : 0.0;
       __syncthreads();
-      if (tid < keep) L.G[tid * 16 + tid] = L.ev[tid];
+      if (tid < keep) {
+        L.G[tid * 16 + tid] = L.ev[tid];
+        L.Lam[tid] = L.ev[tid];
+      }
       mb = keep - 1;
       __syncthreads();
+      IFCI_MARK(kPhRestart);
     }
     // pass B: project out the basis (classical Gram-Schmidt), with a second
     // pass when the norm drops by more than 1/sqrt(2) (DGKS criterion)
     double acc2[kMaxSpace + 1];
 #pragma unroll
     for (int j = 0; j < kMaxSpace + 1; ++j) acc2[j] = 0.0;
-    for (int64_t i = tid; i < ns; i += blockDim.x) {
-      double t = L.tv[i];
-      for (int j = 0; j <= mb; ++j) t -= L.cf[j] * Vb[j * st + i];
-      L.tv[i] = t;
-      acc2[kMaxSpace] += t * t;
+    {
+      double cc[kMaxSpace];
 #pragma unroll
-      for (int j = 0; j < kMaxSpace; ++j)
-        if (j <= mb) acc2[j] += Vb[j * st + i] * t;
+      for (int j = 0; j < kMaxSpace; ++j) cc[j] = (j <= mb) ? L.cf[j] : 0.0;
+      for (int64_t i = tid; i < ns; i += blockDim.x) {
+        double vv[kMaxSpace];
+        double t = L.tv[i];
+#pragma unroll
+        for (int j = 0; j < kMaxSpace; ++j) {
+          vv[j] = (j <= mb) ? Vb[j * st + i] : 0.0;
+          t -= cc[j] * vv[j];
+        }
+        L.tv[i] = t;
+        acc2[kMaxSpace] += t * t;
+#pragma unroll
+        for (int j = 0; j < kMaxSpace; ++j) acc2[j] += vv[j] * t;
+      }
     }
     block_sum<kMaxSpace + 1>(acc2, L.red, L.scal);
     double tt = L.scal[kMaxSpace];
@@ -543,7 +668,15 @@ __device__ __forceinline__ void solve_one(const SolveArgs& A, int pos, char* lds
       Vb[m * st + i] = t;
     }
     __syncthreads();
+    IFCI_MARK(kPhOrtho);
   }
+  if (trace && tid == 0) {
+    ph[kPhIters] = iters;
+    ph[kPhTotal] = clock64() - t_start;
+#pragma unroll
+    for (int q = 0; q < kPhases; ++q) A.phase[(int64_t)id * kPhases + q] = ph[q];
+  }
+#undef IFCI_MARK
   if (tid == 0) {
     const double e = theta + E0 + B[ib.misc + 0] + A.e_const;
     if (A.e_out) A.e_out[o] = e;
@@ -577,11 +710,9 @@ template <int K>
 __device__ void sigma_one(const IncDev d, const double* __restrict__ ints, const int32_t* __restrict__ tables,
                           const double* __restrict__ c, double* __restrict__ sig, int precision,
                           char* lds, int lds_bytes) {
-  const int nw = blockDim.x >> 6;
-  Lds L = carve(lds, d, lds_bytes, nw);
-  const int n = d.n_str, np = d.npair;
-  for (int i = threadIdx.x; i < n * np; i += blockDim.x) L.ptab[i] = tables[d.pair_off + i];
-  for (int i = threadIdx.x; i < n * d.n_link; i += blockDim.x) L.links[i] = tables[d.link_off + i];
+  Lds L = carve(lds, d, lds_bytes);
+  const int n = d.n_str;
+  load_tables(d, L, tables);
   for (int64_t i = threadIdx.x; i < d.n_sym; i += blockDim.x) {
     int a, b;
     unpack(i, &a, &b);
@@ -623,9 +754,16 @@ __global__ void __launch_bounds__(kBatchThreads) sigma_one_kernel(const IncDev* 
   }
 }
 
+// LDS the batched solver needs for an increment: the persistent part plus
+// the larger of the transient part and one FP64 E slice.
 int64_t batched_lds_bytes(int k, int n_str, int n_link) {
-  // fixed part plus one FP64 E slice per wave for at least one wave
-  return batched_fixed_bytes(k, n_str, n_link) + et_slice_bytes(k, n_str, 8);
+  const int64_t tr = transient_bytes(n_str), sl = et_slice_bytes(k, n_str, 8);
+  return persistent_bytes(k, n_str, n_link) + (tr > sl ? tr : sl);
+}
+// LDS that gives every wave of the workgroup its FP64 E slice.
+int64_t batched_lds_want(int k, int n_str, int n_link) {
+  const int64_t tr = transient_bytes(n_str), sl = (kBatchThreads / 64) * et_slice_bytes(k, n_str, 8);
+  return persistent_bytes(k, n_str, n_link) + (tr > sl ? tr : sl);
 }
 
 hipError_t launch_batched(const SolveArgs& A, int lds_bytes, hipStream_t st) {

@@ -86,32 +86,40 @@ constexpr double kRSqrt2 = 0.70710678118654752440;
 
 // Eigen-decomposition of the symmetric n x n matrix A (row stride 16,
 // n <= 16) by cyclic Jacobi rotations (Golub & Van Loan, symmetric Schur
-// decomposition).  Executed by one full wavefront; A is overwritten, Q
-// (stride 16) receives the eigenvectors, evals/perm the sorted eigenvalues
-// and their columns, theta/y the lowest pair.  Lane i owns row i.
-__device__ inline void jacobi_lowest(double* A, double* Q, int n, double* theta, double* y, double* evals,
-                                     int* perm) {
+// decomposition), accumulating the rotations into Q (stride 16), which the
+// caller initialises (identity, or eigenvectors of a previous nearby matrix
+// to warm start).  Rotations whose off-diagonal element is below
+// 1e-15 ||A||_F are skipped; sweeps stop when none is applied.
+// Executed by one full wavefront; lane i owns row i.  Returns the sorted
+// eigenvalues in evals, their columns of Q in perm, and the lowest pair in
+// theta / y.
+__device__ inline void jacobi_warm(double* A, double* Q, int n, double* theta, double* y, double* evals,
+                                   int* perm) {
   const int lane = threadIdx.x & 63;
-  if (lane < n)
-    for (int j = 0; j < n; ++j) Q[lane * 16 + j] = (lane == j) ? 1.0 : 0.0;
   __builtin_amdgcn_wave_barrier();
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    double off = 0.0, all = 0.0;
-    if (lane < n)
-      for (int j = 0; j < n; ++j) {
-        double a = A[lane * 16 + j];
-        all += a * a;
-        if (j != lane) off += a * a;
-      }
-    off = wave_sum(off);
-    all = wave_sum(all);
-    if (!(off > 1e-32 * all)) break;
+  // rotations below 1e-15 ||A||_F are skipped: the eigenvalue error that
+  // leaves is of order 1e-30 ||A||^2 / gap, and FP64 rounding keeps
+  // regenerating off-diagonal noise near 1e-16 ||A|| that must not be chased
+  double f2 = 0.0;
+  if (lane < n)
+    for (int j = 0; j < n; ++j) f2 += A[lane * 16 + j] * A[lane * 16 + j];
+  f2 = wave_sum(f2);
+  const double tol = 1e-15 * sqrt(f2);
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    bool rotated = false;
     for (int p = 0; p < n - 1; ++p) {
-      for (int q = p + 1; q < n; ++q) {
+      // which q > p start this row above the threshold
+      __builtin_amdgcn_wave_barrier();
+      const bool big = lane > p && lane < n && fabs(A[p * 16 + lane]) > tol;
+      uint64_t mask = __ballot(big);
+      while (mask) {
+        const int q = __builtin_ctzll(mask);
+        mask &= mask - 1;
         __builtin_amdgcn_wave_barrier();
         const double apq = A[p * 16 + q];
-        if (apq == 0.0) continue;
+        if (!(fabs(apq) > tol)) continue;
         const double app = A[p * 16 + p], aqq = A[q * 16 + q];
+        rotated = true;
         const double tau = (aqq - app) / (2.0 * apq);
         const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
         const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
@@ -138,6 +146,7 @@ __device__ inline void jacobi_lowest(double* A, double* Q, int n, double* theta,
       }
     }
     __builtin_amdgcn_wave_barrier();
+    if (!rotated) break;
   }
   __builtin_amdgcn_wave_barrier();
   // eigenvalues in increasing order (ties by index): perm[i] is the column
@@ -160,6 +169,15 @@ __device__ inline void jacobi_lowest(double* A, double* Q, int n, double* theta,
   __builtin_amdgcn_wave_barrier();
   if (lane < n) y[lane] = Q[lane * 16 + perm[0]];
   __builtin_amdgcn_wave_barrier();
+}
+
+// Cold-start variant: Q = I, then jacobi_warm.
+__device__ inline void jacobi_lowest(double* A, double* Q, int n, double* theta, double* y, double* evals,
+                                     int* perm) {
+  const int lane = threadIdx.x & 63;
+  if (lane < 16)
+    for (int j = 0; j < 16; ++j) Q[lane * 16 + j] = (lane == j) ? 1.0 : 0.0;
+  jacobi_warm(A, Q, n, theta, y, evals, perm);
 }
 
 }  // namespace ifci

@@ -84,7 +84,11 @@ struct SolveArgs {
   double* resid_out;
   const uint8_t* evict;
   double e_const;
+  int64_t* phase;   // optional [n_inc][kPhases] clock counters (tracing)
 };
+
+// Phases recorded by the tracing counters of the batched solver.
+enum Phase { kPhPrologue = 0, kPhSigma, kPhSubspace, kPhPassA, kPhRestart, kPhOrtho, kPhIters, kPhTotal, kPhases };
 
 __host__ __device__ inline int64_t tri(int64_t b) { return b * (b + 1) / 2; }
 

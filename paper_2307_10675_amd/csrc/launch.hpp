@@ -14,6 +14,7 @@ hipError_t launch_embed(const IncDev* incs, int n_inc, const int32_t* orbs, cons
                         double e_const, double* misc, hipStream_t st);
 
 int64_t batched_lds_bytes(int k, int n_str, int n_link);
+int64_t batched_lds_want(int k, int n_str, int n_link);
 hipError_t launch_batched(const SolveArgs& A, int lds_bytes, hipStream_t st);
 hipError_t launch_sigma_one(const IncDev* incs, int inc, const double* ints, const int32_t* tables,
                             const double* c, double* sig, int precision, int lds_bytes,

@@ -48,6 +48,7 @@ struct ifci_plan_s {
   int8_t* d_loc = nullptr;           // [n_inc + 1][n_orb] orbital roles
   double* d_w_inc = nullptr;         // expansion weight of every increment
   bool on_device = false;
+  int64_t* phase_counters = nullptr;  // tracing: per-increment phase clocks
   std::vector<int32_t> h_sub_ptr, h_sub_idx, h_inc_size;
   std::vector<int8_t> h_loc;
   std::vector<double> h_w_inc;

@@ -68,6 +68,7 @@ _SIGNATURES = {
                                    ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "ifci_rdm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.c_void_p]),
+    "ifci_set_phase_counters": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
     "ifci_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ifci_last_error": (ctypes.c_char_p, []),
 }
@@ -237,6 +238,19 @@ class Plan:
         _check(lib().ifci_davidson(self._h, first, count, _ptr(e), _ptr(st), _ptr(ev), _ptr(it), _ptr(rs),
                                    _stream(stream)))
         return e, st, it, rs
+
+    def trace_phases(self, enable: bool = True):
+        """Per-increment phase clock counters of the batched solver (int64
+        [n_inc][8]: set-up, sigma, subspace, residual, restart, orthogonalise,
+        sigma count, total); returns the torch buffer the next davidson fills."""
+        import torch
+        if not enable:
+            _check(lib().ifci_set_phase_counters(self._h, None, 0))
+            self._phase = None
+            return None
+        self._phase = torch.zeros((self.n_inc, 8), dtype=torch.int64, device=torch.device("cuda", self.device))
+        _check(lib().ifci_set_phase_counters(self._h, _ptr(self._phase), self._phase.numel()))
+        return self._phase
 
     def vector(self, inc: int, stream=None):
         import torch
