@@ -35,7 +35,9 @@ namespace ifci {
 
 struct Lds {
   // persistent
-  int32_t* ptab;   // [n_str][np] decoded pair table: J | neg << 16, J = n_str if no link
+  int32_t* ptab;   // two int16 [n_str + 1][npair_pad] decoded pair tables: J (n+1) | neg << 15
+                   // and J | neg << 15, with J = n_str for no link (and for the
+                   // sentinel last row and the padding pairs)
   int32_t* links;  // [n_str][n_link]  (Q << 17 | J << 1 | neg)
   int32_t* strs;   // [n_str]
   double* F;       // [n_str] string energies
@@ -65,13 +67,21 @@ struct Lds {
 
 __host__ __device__ inline int64_t a16(int64_t x) { return (x + 15) & ~int64_t(15); }
 
+// CI vector in LDS: FP64 packed with a zero tail of n+1 entries, or FP32
+// full (n+1) x (n+1) with a zero last row and column.
 __host__ __device__ inline int64_t cp_bytes(int n_str) {
-  const int64_t a = 8 * tri(n_str), b = 4 * (int64_t)(n_str + 1) * (n_str + 1);
+  const int64_t a = 8 * (tri(n_str) + n_str + 1), b = 4 * (int64_t)(n_str + 1) * (n_str + 1);
   return a16(a > b ? a : b);
 }
+// pair count padded to the MFMA k-step
+__host__ __device__ inline int npair_pad(int k) { return (k * (k + 1) / 2 + 3) / 4 * 4; }
+// two int16 tables of (n+1) x npair_pad entries
+__host__ __device__ inline int64_t ptab_bytes(int k, int n_str) {
+  return a16(2 * 2 * (int64_t)(n_str + 1) * npair_pad(k));
+}
 __host__ __device__ inline int64_t persistent_bytes(int k, int n_str, int n_link) {
-  const int64_t np = (int64_t)k * (k + 1) / 2, ns = tri(n_str);
-  return a16(4 * n_str * np) + a16(4 * (int64_t)n_str * n_link) + a16(4 * n_str) + a16(8 * n_str) +
+  const int64_t ns = tri(n_str);
+  return ptab_bytes(k, n_str) + a16(4 * (int64_t)n_str * n_link) + a16(4 * n_str) + a16(8 * n_str) +
          a16(8 * (2 * k * k + k)) + 8 * (256 + 256 + 16) + cp_bytes(n_str) + a16(8 * ns);
 }
 __host__ __device__ inline int64_t transient_bytes(int n_str) {
@@ -88,7 +98,8 @@ __device__ inline Lds carve(char* base, const IncDev& d, int lds_bytes) {
   char* p = base;
   const int n = d.n_str, np = d.npair, k = d.k;
   L.ptab = (int32_t*)p;
-  p += a16(4 * n * np);
+  p += ptab_bytes(k, n);
+  (void)np;
   L.links = (int32_t*)p;
   p += a16(4 * n * d.n_link);
   L.strs = (int32_t*)p;
@@ -190,50 +201,62 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
   constexpr bool kFull = sizeof(T) == 4;  // FP32: full (n+1)^2 layout, FP64: packed
   const int ld = n + 1;
 
+  constexpr int NPp = 4 * KS;
+  const int16_t* ptA = (const int16_t*)L.ptab;    // [a][Q]: J (n + 1) | neg << 15
+  const int16_t* ptB = ptA + (n + 1) * NPp;       // [a][Q]: J | neg << 15
+
+  // B operand of one MFMA step: D[Q][(a, b)] = sign1 c[J1][b] + sign2 c[a][J2]
+  // for Q = 4 s + kq.  A missing link, a padding pair and the sentinel row
+  // (a >= n) all carry J = n, which addresses zeros (the zero row / column of
+  // the full layout, the zero tail of the packed one): every load is
+  // unconditional and there is no branch.
+  auto bval = [&](int ar, int arow, int s, int e2, int b) -> T {
+    const int e1 = ptA[arow + 4 * s + kq];
+    T v1, v2;
+    if (kFull) {
+      v1 = cp[(e1 & 0x7FFF) + b];
+      v2 = cp[ar * ld + (e2 & 0x7FFF)];
+    } else {
+      v1 = cp[pk32(ptB[arow + 4 * s + kq] & 0x7FFF, b)];
+      v2 = cp[pk32(ar, e2 & 0x7FFF)];
+    }
+    return ((e1 & 0x8000) ? -v1 : v1) + ((e2 & 0x8000) ? -v2 : v2);
+  };
+
   for (int b = wave; b < n; b += et_waves) {
     // beta-part entries of column b, one per k-step of this lane
     int jb[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       const int Q = 4 * s + kq;
-      jb[s] = (Q < NP) ? L.ptab[b * NP + Q] : n;
+      jb[s] = (int)(uint16_t)ptB[b * NPp + Q];
     }
-    for (int nt = 0; nt < nt_count; ++nt) {
-      const int a = nt * 16 + col;
-      const int ac = a < n ? a : n;  // a padding row reads zeros (full layout)
-      typename M::acc acc[MT];
+    // two 16-determinant tiles at a time: six independent MFMA chains
+    for (int nt = 0; nt < nt_count; nt += 2) {
+      const int a0 = min(nt * 16 + col, n), a1 = min(nt * 16 + 16 + col, n);  // n: sentinel
+      const int r0 = a0 * NPp, r1 = a1 * NPp;
+      typename M::acc acc0[MT], acc1[MT];
 #pragma unroll
-      for (int m = 0; m < MT; ++m) acc[m] = M::zero();
+      for (int m = 0; m < MT; ++m) acc0[m] = acc1[m] = M::zero();
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        // D[Q][(a,b)] = sign1 c[J1][b] + sign2 c[a][J2]; a missing link has
-        // J = n, which addresses the zero row / column (full layout)
-        const int Q = 4 * s + kq;
-        const int e1 = (a < n && Q < NP) ? L.ptab[a * NP + Q] : n;
-        const int e2 = jb[s];
-        T v1, v2;
-        if (kFull) {
-          v1 = cp[(e1 & 0xFFFF) * ld + b];
-          v2 = cp[ac * ld + (e2 & 0xFFFF)];
-        } else {
-          // packed layout: clamp to a valid entry, then zero the missing links
-          const int J1 = e1 & 0xFFFF, J2 = e2 & 0xFFFF;
-          const int a0 = a < n ? a : 0;
-          v1 = cp[pk32(J1 < n ? J1 : 0, b)];
-          v2 = cp[pk32(a0, J2 < n ? J2 : 0)];
-          v1 = (J1 < n) ? v1 : (T)0;
-          v2 = (J2 < n && a < n) ? v2 : (T)0;
-        }
-        const T bv = ((e1 >> 16) ? -v1 : v1) + ((e2 >> 16) ? -v2 : v2);
+        const T b0 = bval(a0, r0, s, jb[s], b);
+        const T b1 = bval(a1, r1, s, jb[s], b);
 #pragma unroll
-        for (int m = 0; m < MT; ++m) acc[m] = M::mma(afr[m][s], bv, acc[m]);
+        for (int m = 0; m < MT; ++m) {
+          acc0[m] = M::mma(afr[m][s], b0, acc0[m]);
+          acc1[m] = M::mma(afr[m][s], b1, acc1[m]);
+        }
       }
 #pragma unroll
       for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int P = 16 * m + M::row(kq, r);
-          if (P < NP) et[P * nbp + nt * 16 + col] = acc[m][r];
+          if (m < MT - 1 || P < NP) {
+            et[P * nbp + nt * 16 + col] = acc0[m][r];
+            if (nt + 1 < nt_count) et[P * nbp + nt * 16 + 16 + col] = acc1[m][r];
+          }
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -257,12 +280,18 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
   }
 }
 
-// Pair table (decoded: J | neg << 16, J = n_str for no link) and link lists into LDS.
+// Pair tables (decoded, see Lds::ptab) and link lists into LDS.
 __device__ inline void load_tables(const IncDev& d, const Lds& L, const int32_t* __restrict__ tables) {
   const int n = d.n_str, np = d.npair;
-  for (int i = threadIdx.x; i < n * np; i += blockDim.x) {
-    const int e = tables[d.pair_off + i];
-    L.ptab[i] = e < 0 ? n : ((e >> 1) | ((e & 1) << 16));
+  const int npp = npair_pad(d.k);
+  int16_t* ptA = (int16_t*)L.ptab;
+  int16_t* ptB = ptA + (n + 1) * npp;
+  for (int i = threadIdx.x; i < (n + 1) * npp; i += blockDim.x) {
+    const int a = i / npp, Q = i - a * npp;
+    const int e = (a < n && Q < np) ? tables[d.pair_off + a * np + Q] : -1;
+    const int J = e < 0 ? n : (e >> 1), neg = e < 0 ? 0 : (e & 1);
+    ptA[i] = (int16_t)(J * (n + 1) | (neg << 15));
+    ptB[i] = (int16_t)(J | (neg << 15));
   }
   for (int i = threadIdx.x; i < n * d.n_link; i += blockDim.x) L.links[i] = tables[d.link_off + i];
 }
@@ -293,6 +322,7 @@ __device__ inline void prepare_sigma(const IncDev& d, const Lds& L) {
       cp[i] = (T)(a == b ? v : v * kRSqrt2);
       L.sp[i] = 0.0;
     }
+    for (int i = threadIdx.x; i <= n; i += blockDim.x) cp[d.n_sym + i] = (T)0;  // zero tail
   }
   __syncthreads();
 }
@@ -686,6 +716,325 @@ __device__ __forceinline__ void solve_one(const SolveArgs& A, int pos, char* lds
   }
 }
 
+// Lowest eigenpair of the symmetric 3 x 3 matrix g by cyclic Jacobi
+// rotations in registers (every loop has fixed bounds, so nothing is
+// indexed dynamically).  A 2 x 2 problem is passed with g[2][2] far above
+// the spectrum and a zero last row.  Returns theta and z (unit).
+__device__ inline void small_eig3(double g[3][3], double* theta, double z[3]) {
+  double v[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+#pragma unroll 1
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    // per-pair test: a decoupled sentinel row must not mask the others
+    bool rotated = false;
+#pragma unroll
+    for (int pq = 0; pq < 3; ++pq) {
+      const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+      const double apq = g[p][q];
+      if (fabs(apq) > 1e-17 * (fabs(g[p][p]) + fabs(g[q][q])) && fabs(apq) > 1e-300) {
+        rotated = true;
+        const double tau = (g[q][q] - g[p][p]) / (2.0 * apq);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const double gip = g[i][p], giq = g[i][q];
+          g[i][p] = c * gip - sn * giq;
+          g[i][q] = sn * gip + c * giq;
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const double gpi = g[p][i], gqi = g[q][i];
+          g[p][i] = c * gpi - sn * gqi;
+          g[q][i] = sn * gpi + c * gqi;
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const double vp = v[i][p], vq = v[i][q];
+          v[i][p] = c * vp - sn * vq;
+          v[i][q] = sn * vp + c * vq;
+        }
+      }
+    }
+    if (!rotated) break;
+  }
+  // lowest diagonal entry and its column
+  const int im = (g[1][1] < g[0][0]) ? ((g[2][2] < g[1][1]) ? 2 : 1) : ((g[2][2] < g[0][0]) ? 2 : 0);
+  *theta = im == 0 ? g[0][0] : (im == 1 ? g[1][1] : g[2][2]);
+  double nz = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    z[i] = im == 0 ? v[i][0] : (im == 1 ? v[i][1] : v[i][2]);
+    nz += z[i] * z[i];
+  }
+  nz = 1.0 / sqrt(nz);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) z[i] *= nz;
+}
+
+// Locally optimal block-free iteration (Davidson restarted every step to the
+// three vectors {x, w, p}: the Ritz vector, its preconditioned residual and
+// the previous search direction; LOBPCG with block size one).  The basis is
+// kept orthonormal: w is orthogonalised against x and p (classical
+// Gram-Schmidt, repeated when the norm drops by more than 1/sqrt(2)), and the
+// new direction p is built from the Rayleigh-Ritz coefficients already
+// orthogonal to the new x.  Vectors: x, w, p in V[0..2], their sigmas in
+// S[0..2], w also in LDS for the next sigma.
+template <int K>
+__device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* lds, int lds_bytes) {
+  const int id = A.order[pos];
+  const IncDev d = A.inc[id];
+  Lds L = carve(lds, d, lds_bytes);
+  const double* B = A.ints + d.int_off;
+  const IntBlock ib = int_block(d.k);
+  const double* Vm = B + ib.V;
+  const int64_t ns = d.n_sym, st = d.stride;
+  double* base = A.dav + d.vec_off;
+  const int mmax = A.max_space;
+  double* xv = base;
+  double* wv = base + st;
+  double* pv = base + 2 * st;
+  double* ax = base + mmax * st;
+  double* aw = ax + st;
+  double* ap = ax + 2 * st;
+  double* HD = base + 2 * mmax * st;
+  double* X = HD + st;
+  const int tid = threadIdx.x;
+  int64_t ph[kPhases];
+#pragma unroll
+  for (int q = 0; q < kPhases; ++q) ph[q] = 0;
+  const bool trace = A.phase != nullptr;
+  int64_t t_start = trace ? clock64() : 0, t_mark = t_start;
+#define IFCI_MARK(PH)                      \
+  if (trace) {                             \
+    const int64_t now_ = clock64();        \
+    ph[PH] += now_ - t_mark;               \
+    t_mark = now_;                         \
+  }
+
+  load_increment(d, L, A.tables, B, HD);
+  argmin_block(HD, ns, L);
+  const double E0 = L.scal[0];
+  const int64_t guess = L.iscal[0];
+  for (int64_t i = tid; i < ns; i += blockDim.x) {
+    const double v = (i == guess) ? 1.0 : 0.0;
+    L.tv[i] = v;
+    xv[i] = v;
+  }
+  __syncthreads();
+  IFCI_MARK(kPhPrologue);
+
+  const int ew64 = et_waves_for<double, K>(d, L);
+  const int ew32 = et_waves_for<float, K>(d, L);
+  int phase = (A.precision == IFCI_MIXED) ? 32 : 64;
+  int iters = 0, status = IFCI_INC_NOT_CONVERGED;
+  double theta = 0.0, resid = 1e300;
+  const int64_t o = (int64_t)id - A.first;
+  const bool evict = A.evict && A.evict[o] != 0;
+  bool fresh = true;     // x has no sigma yet (start or precision switch)
+  bool have_p = false;
+  double xap = 0.0, pap = 0.0;  // x.Ap and p.Ap of the current basis
+
+  while (true) {
+    // ---- sigma of the vector in L.tv (x when fresh, else w)
+    if (phase == 32)
+      sigma_phase<float, K>(d, L, Vm, E0, ew32);
+    else
+      sigma_phase<double, K>(d, L, Vm, E0, ew64);
+    ++iters;
+    IFCI_MARK(kPhSigma);
+    double gxw = 0.0, gww = 0.0, gpw = 0.0;
+    if (fresh) {
+      // ax = sigma(x), theta = x.Ax
+      double acc[1] = {0.0};
+      for (int64_t i = tid; i < ns; i += blockDim.x) {
+        const double s = L.sp[i];
+        ax[i] = s;
+        acc[0] += xv[i] * s;
+      }
+      block_sum<1>(acc, L.red, L.scal);
+      theta = L.scal[0];
+      have_p = false;
+    } else {
+      // aw = sigma(w) and the new column of the 3 x 3 Rayleigh-Ritz matrix
+      double acc[3] = {0.0, 0.0, 0.0};
+      for (int64_t i = tid; i < ns; i += blockDim.x) {
+        const double s = L.sp[i];
+        aw[i] = s;
+        acc[0] += xv[i] * s;
+        acc[1] += wv[i] * s;
+        if (have_p) acc[2] += pv[i] * s;
+      }
+      block_sum<3>(acc, L.red, L.scal);
+      gxw = L.scal[0];
+      gww = L.scal[1];
+      gpw = L.scal[2];
+    }
+    IFCI_MARK(kPhSubspace);
+    // ---- Rayleigh-Ritz on span{x, w, p} and the update pass
+    double cx[3] = {1.0, 0.0, 0.0}, cpv[3] = {0.0, 0.0, 0.0};
+    bool new_p = false;
+    if (!fresh) {
+      // (without p the third basis vector is decoupled and placed far above)
+      const double big = 1e30;
+      double g[3][3] = {{theta, gxw, have_p ? xap : 0.0},
+                        {gxw, gww, have_p ? gpw : 0.0},
+                        {have_p ? xap : 0.0, have_p ? gpw : 0.0, have_p ? pap : big}};
+      double z[3];
+      double th;
+      small_eig3(g, &th, z);
+      if (!have_p) z[2] = 0.0;
+      if (z[0] < 0.0) {
+        z[0] = -z[0];
+        z[1] = -z[1];
+        z[2] = -z[2];
+      }
+      // new x and the direction p'' = (z1 w + z2 p) orthogonalised against x'
+      const double rho = z[1] * z[1] + z[2] * z[2];
+      cx[0] = z[0];
+      cx[1] = z[1];
+      cx[2] = z[2];
+      const double pn = z[0] * sqrt(rho);
+      if (pn > 1e-14) {
+        cpv[0] = -rho * z[0] / pn;
+        cpv[1] = z[0] * z[0] * z[1] / pn;
+        cpv[2] = z[0] * z[0] * z[2] / pn;
+        new_p = true;
+      }
+      // x'.Ap'' and p''.Ap'' from the 3 x 3 matrix (g was overwritten)
+      const double G3[3][3] = {{theta, gxw, xap}, {gxw, gww, gpw}, {xap, gpw, pap}};
+      double gx[3], gp[3];
+      for (int i = 0; i < 3; ++i) {
+        gx[i] = 0.0;
+        gp[i] = 0.0;
+        for (int j = 0; j < 3; ++j) {
+          gx[i] += G3[i][j] * cx[j];
+          gp[i] += G3[i][j] * cpv[j];
+        }
+      }
+      double nxap = 0.0, npap = 0.0;
+      for (int i = 0; i < 3; ++i) {
+        nxap += cx[i] * gp[i];
+        npap += cpv[i] * gp[i];
+      }
+      theta = th;
+      xap = nxap;
+      pap = npap;
+    }
+    // update x, ax, p, ap in place; residual r = ax - theta x; correction
+    // w = r / (theta - (H_II - E0)) into LDS with its overlaps with x', p'
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = tid; i < ns; i += blockDim.x) {
+      double x = xv[i], sx = ax[i];
+      double pnew = 0.0, apnew = 0.0;
+      if (!fresh) {
+        const double w = wv[i], sw = aw[i];
+        const double pp = have_p ? pv[i] : 0.0, sp = have_p ? ap[i] : 0.0;
+        const double xn = cx[0] * x + cx[1] * w + cx[2] * pp;
+        const double sxn = cx[0] * sx + cx[1] * sw + cx[2] * sp;
+        pnew = cpv[0] * x + cpv[1] * w + cpv[2] * pp;
+        apnew = cpv[0] * sx + cpv[1] * sw + cpv[2] * sp;
+        x = xn;
+        sx = sxn;
+        xv[i] = x;
+        ax[i] = sx;
+        if (new_p) {
+          pv[i] = pnew;
+          ap[i] = apnew;
+        }
+      }
+      const double r = sx - theta * x;
+      double den = theta - (HD[i] - E0);
+      if (fabs(den) < 1e-8) den = (den < 0.0) ? -1e-8 : 1e-8;
+      const double t = r / den;
+      L.tv[i] = t;
+      acc[0] += r * r;
+      acc[1] += t * t;
+      acc[2] += x * t;
+      acc[3] += pnew * t;
+    }
+    block_sum<6>(acc, L.red, L.scal);
+    resid = sqrt(L.scal[0]);
+    const double tt0 = L.scal[1];
+    const double dxw = L.scal[2];
+    const double dpw = new_p ? L.scal[3] : 0.0;
+    have_p = new_p || (have_p && fresh);
+    if (fresh) have_p = false;
+    fresh = false;
+    IFCI_MARK(kPhPassA);
+
+    const double tol = (phase == 32) ? A.r_tol_inner : A.r_tol;
+    if (evict) {
+      status = IFCI_INC_EVICTED;
+      break;
+    }
+    if (resid <= tol) {
+      if (phase == 32) {
+        // FP64 refinement: sigma of x in FP64, then continue in FP64
+        phase = 64;
+        for (int64_t i = tid; i < ns; i += blockDim.x) L.tv[i] = xv[i];
+        fresh = true;
+        __syncthreads();
+        if (iters >= A.max_iter) break;
+        continue;
+      }
+      status = IFCI_INC_DONE;
+      break;
+    }
+    if (iters >= A.max_iter) break;
+    // ---- orthogonalise w against x and p, normalise, store
+    double acc2[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = tid; i < ns; i += blockDim.x) {
+      double t = L.tv[i] - dxw * xv[i];
+      if (have_p) t -= dpw * pv[i];
+      L.tv[i] = t;
+      acc2[0] += t * t;
+      acc2[1] += xv[i] * t;
+      if (have_p) acc2[2] += pv[i] * t;
+    }
+    block_sum<3>(acc2, L.red, L.scal);
+    double tt = L.scal[0];
+    if (tt < 0.5 * tt0) {
+      const double c0 = L.scal[1], c1 = L.scal[2];
+      __syncthreads();
+      double acc3[1] = {0.0};
+      for (int64_t i = tid; i < ns; i += blockDim.x) {
+        double t = L.tv[i] - c0 * xv[i];
+        if (have_p) t -= c1 * pv[i];
+        L.tv[i] = t;
+        acc3[0] += t * t;
+      }
+      block_sum<1>(acc3, L.red, L.scal);
+      tt = L.scal[0];
+    }
+    __syncthreads();
+    if (!(tt > 1e-28)) break;  // no new direction: stagnated
+    const double inv = 1.0 / sqrt(tt);
+    for (int64_t i = tid; i < ns; i += blockDim.x) {
+      const double t = L.tv[i] * inv;
+      L.tv[i] = t;
+      wv[i] = t;
+    }
+    __syncthreads();
+    IFCI_MARK(kPhOrtho);
+  }
+  for (int64_t i = tid; i < ns; i += blockDim.x) X[i] = xv[i];
+  if (trace && tid == 0) {
+    ph[kPhIters] = iters;
+    ph[kPhTotal] = clock64() - t_start;
+#pragma unroll
+    for (int q = 0; q < kPhases; ++q) A.phase[(int64_t)id * kPhases + q] = ph[q];
+  }
+#undef IFCI_MARK
+  if (tid == 0) {
+    const double e = theta + E0 + B[ib.misc + 0] + A.e_const;
+    if (A.e_out) A.e_out[o] = e;
+    if (A.status_out) A.status_out[o] = status;
+    if (A.iters_out) A.iters_out[o] = iters;
+    if (A.resid_out) A.resid_out[o] = resid;
+  }
+}
+
+// One kernel per solver so that each gets its own register allocation.
 __global__ void __launch_bounds__(kBatchThreads) batched_kernel(SolveArgs A, int lds_bytes) {
   extern __shared__ __align__(16) char lds[];
   const int pos = blockIdx.x;
@@ -700,6 +1049,24 @@ __global__ void __launch_bounds__(kBatchThreads) batched_kernel(SolveArgs A, int
     case 6: solve_one<6>(A, pos, lds, lds_bytes); break;
     case 7: solve_one<7>(A, pos, lds, lds_bytes); break;
     case 8: solve_one<8>(A, pos, lds, lds_bytes); break;
+    default: break;
+  }
+}
+
+__global__ void __launch_bounds__(kBatchThreads) batched_lobpcg_kernel(SolveArgs A, int lds_bytes) {
+  extern __shared__ __align__(16) char lds[];
+  const int pos = blockIdx.x;
+  if (pos >= A.count) return;
+  const int k = A.inc[A.order[pos]].k;
+  switch (k) {
+    case 1: solve_lobpcg<1>(A, pos, lds, lds_bytes); break;
+    case 2: solve_lobpcg<2>(A, pos, lds, lds_bytes); break;
+    case 3: solve_lobpcg<3>(A, pos, lds, lds_bytes); break;
+    case 4: solve_lobpcg<4>(A, pos, lds, lds_bytes); break;
+    case 5: solve_lobpcg<5>(A, pos, lds, lds_bytes); break;
+    case 6: solve_lobpcg<6>(A, pos, lds, lds_bytes); break;
+    case 7: solve_lobpcg<7>(A, pos, lds, lds_bytes); break;
+    case 8: solve_lobpcg<8>(A, pos, lds, lds_bytes); break;
     default: break;
   }
 }
@@ -771,10 +1138,16 @@ hipError_t launch_batched(const SolveArgs& A, int lds_bytes, hipStream_t st) {
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)batched_kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)batched_lobpcg_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kMaxLds);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(batched_kernel, dim3(A.count), dim3(kBatchThreads), lds_bytes, st, A, lds_bytes);
+  if (A.max_space == 3)
+    hipLaunchKernelGGL(batched_lobpcg_kernel, dim3(A.count), dim3(kBatchThreads), lds_bytes, st, A, lds_bytes);
+  else
+    hipLaunchKernelGGL(batched_kernel, dim3(A.count), dim3(kBatchThreads), lds_bytes, st, A, lds_bytes);
   return hipGetLastError();
 }
 
