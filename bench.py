@@ -5,8 +5,9 @@ truncation: 16 + 120 + 560 + 1820 increments of 2o2e, 4o4e, 6o6e and 8o8e
 (2516 increments, 9,146,384 determinants), seeded synthetic integrals.
 
 One step = embed every increment (frozen-core integrals, H diagonal),
-solve every increment (batched persistent Davidson, FP32 MFMA sigma with
-FP64 subspace and FP64 residual refinement) and assemble the expansion
+solve every increment (batched persistent solver, one workgroup per
+increment, three-vector {x, w, p} iteration, FP32 MFMA sigma with FP64
+subspace and FP64 residual refinement) and assemble the expansion
 energies (eqs. 2-5).  The metric counts increments whose energy is within
 1 uEh of the FP64 solution, per second of step time.  The FP64 batched path
 and the plain per-increment FP64 path are timed beside it, and the CPU
@@ -29,7 +30,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp64_mfma": 78.6e12, "fp32_mfma": 157.3e12, "hbm": 8.0e12}
+KERNEL_SOURCES = ["batched.hip", "device_common.hpp", "ifci_internal.h", "launch.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batched_lobpcg_kernel_workload2.traffic.json")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    m = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2307_10675_amd", "csrc", f), "rb") as fh:
+            m.update(fh.read())
+    return m.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the batched kernel (mixed leg) from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE passes, each scaled by the
+    same counter's reading for a device copy of known size; None when the
+    kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except OSError:
+        return None
+    if t.get("source_sha256") != kernel_source_hash():
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
 TOL_UEH = 1e-6
+SPACE = 3  # batched solver subspace: 3 = {x, w, p} iteration (12 = thick-restart Davidson)
 
 
 def f_sym(k: int, na: int) -> float:
@@ -106,6 +134,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device three times (a kernel of known "
+                         "traffic, to scale HBM byte counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the increments are independent and would be "
@@ -117,6 +148,13 @@ def main():
 
     problem = synthetic.workload(2)
     dev = torch.device("cuda", 0)
+    if a.copy_calibration > 0:
+        src = torch.ones(a.copy_calibration << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     h = torch.tensor(problem.h, dtype=torch.float64, device=dev)
     eri = torch.tensor(problem.eri, dtype=torch.float64, device=dev).contiguous()
 
@@ -129,7 +167,7 @@ def main():
     flops = np.array([f_sym(i.n_act, i.n_alpha) for i in incs])
 
     def measure(precision, solver, steps, warmup, **kw):
-        plan = ifci.Plan(problem, precision=precision, solver=solver, max_iter=300, **kw).attach(h, eri)
+        plan = ifci.Plan(problem, precision=precision, solver=solver, max_iter=500, **kw).attach(h, eri)
         (e, st, it, en, _), wall, kms = run_steps(plan, h, eri, steps, warmup, torch)
         e = e.cpu().numpy()
         it = it.cpu().numpy()
@@ -139,11 +177,13 @@ def main():
                     sigma_flops=float((it * flops).sum()), mean_iters=float(it.mean()), total=en["total"])
 
     # headline: batched mixed precision at 1 uEh
-    mixed = measure(ifci.MIXED, ifci.BATCHED, a.steps, a.warmup, r_tol=3e-5, r_tol_inner=1e-5)
-    fp64 = measure(ifci.FP64, ifci.BATCHED, max(1, a.steps // 2), 1, r_tol=3e-5)
+    mixed = measure(ifci.MIXED, ifci.BATCHED, a.steps, a.warmup, r_tol=3e-5, r_tol_inner=1e-5,
+                    max_space=SPACE)
+    fp64 = measure(ifci.FP64, ifci.BATCHED, max(1, a.steps // 2), 1, r_tol=3e-5, max_space=SPACE)
     plain = None if a.no_plain else measure(ifci.FP64, ifci.PLAIN, 1, 0, r_tol=3e-5)
 
     kern_s = mixed["kernel_ms"] * 1e-3
+    traffic = measured_traffic()
     achieved = mixed["sigma_flops"] / kern_s
     out = {
         "metric": "iFCI increments/sec at 1 uEh (batched mixed-precision solver)",
@@ -161,17 +201,18 @@ def main():
         "config": {
             "workload": "16 bodies x (2 orbitals, 2 electrons), 4-body iFCI: 16x2o2e + 120x4o4e + "
                         "560x6o6e + 1820x8o8e = 2516 increments, 9,146,384 determinants, seed 2000",
-            "precision": "mixed", "solver": "batched", "r_tol": 3e-5, "r_tol_inner": 1e-5,
+            "precision": "mixed", "solver": "batched", "max_space": SPACE, "r_tol": 3e-5, "r_tol_inner": 1e-5,
             "accuracy_gate_Eh": TOL_UEH,
         },
         "roofline": {
             "bound": "mfma",
-            "kernel": "batched_kernel (persistent per-increment Davidson, sigma on MFMA)",
+            "kernel": "batched_lobpcg_kernel (one workgroup per increment, sigma on FP32/FP64 MFMA)",
             "achieved": achieved / 1e12,
             "peak": PEAK["fp32_mfma"] / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK["fp32_mfma"],
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         },
         "detail": {
             "mixed_batched": mixed,

@@ -395,12 +395,15 @@ ifci_status ifci_davidson(ifci_plan_t p, int64_t first, int64_t count, double* e
         rest.push_back(i);
     }
   if (!ids.empty()) {
-    // wait for any earlier upload from order_batch before reusing it
-    HIP_TRY(hipStreamSynchronize(st), "ifci_davidson");
-    p->order_batch = ids;
-    HIP_TRY(hipMemcpyAsync(p->d_order, p->order_batch.data(), ids.size() * sizeof(int32_t),
-                           hipMemcpyHostToDevice, st),
-            "ifci_davidson upload");
+    if (ids != p->order_batch) {
+      // a new work list: wait for any earlier upload from order_batch
+      // before reusing its host memory (a repeated list is already there)
+      HIP_TRY(hipStreamSynchronize(st), "ifci_davidson");
+      p->order_batch = ids;
+      HIP_TRY(hipMemcpyAsync(p->d_order, p->order_batch.data(), ids.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, st),
+              "ifci_davidson upload");
+    }
     SolveArgs A;
     A.inc = p->d_inc;
     A.order = p->d_order;

@@ -14,8 +14,12 @@
 //   sigma       = S + S^T     (the beta part of sigma is the transpose of the
 //                              alpha part when C = C^T).
 // Each wavefront owns one beta column b at a time: it computes E for the
-// whole column in its private LDS slice and gathers S[:, b] from it, so no
-// workgroup barrier sits inside the column loop.  The packed sigma slot of
+// whole column in its private LDS slice (stored transposed, E[a][P]) and
+// gathers S[:, b] from it, so no workgroup barrier sits inside the column
+// loop.  The MFMA B operand is built without dependent loads: the alpha
+// part reads a per-wave copy of column b (and its negation) at offsets held
+// in registers for the whole sigma, the beta part reads C at a per-column
+// row offset plus a compile-time tile offset.  The packed sigma slot of
 // (a, b) receives exactly two contributions (from column b and column a),
 // added to zero with LDS atomics; two-term sums are order independent, so
 // the result is deterministic.
@@ -28,16 +32,20 @@
 // the CI vector and the sigma accumulator) and a transient part (working
 // vector, eigensolver scratch, reduction buffers) that the per-wave E slices
 // overlay while sigma runs.
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "launch.hpp"
 
 namespace ifci {
 
 struct Lds {
+  char* root;      // start of the dynamic LDS (byte offsets below are from here)
   // persistent
-  int32_t* ptab;   // two int16 [n_str + 1][npair_pad] decoded pair tables: J (n+1) | neg << 15
-                   // and J | neg << 15, with J = n_str for no link (and for the
-                   // sentinel last row and the padding pairs)
+  char* colb;      // per sigma wave: column b of C and its negation, [2 (n_str + 1)] of T
+  int32_t* ptab;   // int16 [n_str + 1][npair_pad] decoded pair table J | neg << 15, with
+                   // J = n_str for no link (and for the sentinel last row and the
+                   // padding pairs)
   int32_t* links;  // [n_str][n_link]  (Q << 17 | J << 1 | neg)
   int32_t* strs;   // [n_str]
   double* F;       // [n_str] string energies
@@ -47,8 +55,7 @@ struct Lds {
   double* G;       // [16*16] subspace matrix
   double* Qp;      // [16*16] eigenvectors of the previous subspace matrix
   double* Lam;     // [16] its eigenvalues
-  double* cp;      // CI vector: FP64 packed [n_sym]; FP32 full [(n+1)^2] with a zero
-                   // last row and column
+  double* cp;      // CI vector, full (n+1) x (n+1) of T with a zero last row and column
   double* sp;      // [n_sym] sigma accumulator, packed scaled
   // transient (overlaid by the E slices during sigma)
   double* tv;      // [n_sym] working vector, packed scaled
@@ -75,28 +82,43 @@ __host__ __device__ inline int64_t cp_bytes(int n_str) {
 }
 // pair count padded to the MFMA k-step
 __host__ __device__ inline int npair_pad(int k) { return (k * (k + 1) / 2 + 3) / 4 * 4; }
-// two int16 tables of (n+1) x npair_pad entries
+// int16 table of (n+1) x npair_pad entries
 __host__ __device__ inline int64_t ptab_bytes(int k, int n_str) {
-  return a16(2 * 2 * (int64_t)(n_str + 1) * npair_pad(k));
+  return a16(2 * (int64_t)(n_str + 1) * npair_pad(k));
+}
+// column copies: eight waves of floats, or of doubles when that stays small
+__host__ __device__ inline int64_t colb_bytes(int n_str) {
+  const int64_t e = 2 * (int64_t)(n_str + 1);
+  return a16(n_str <= 64 ? 8 * 8 * e : 8 * 4 * e);
 }
 __host__ __device__ inline int64_t persistent_bytes(int k, int n_str, int n_link) {
   const int64_t ns = tri(n_str);
-  return ptab_bytes(k, n_str) + a16(4 * (int64_t)n_str * n_link) + a16(4 * n_str) + a16(8 * n_str) +
-         a16(8 * (2 * k * k + k)) + 8 * (256 + 256 + 16) + cp_bytes(n_str) + a16(8 * ns);
+  return colb_bytes(n_str) + ptab_bytes(k, n_str) + a16(4 * (int64_t)n_str * n_link) + a16(4 * n_str) +
+         a16(8 * n_str) + a16(8 * (2 * k * k + k)) + 8 * (256 + 256 + 16) + cp_bytes(n_str) + a16(8 * ns);
 }
 __host__ __device__ inline int64_t transient_bytes(int n_str) {
   return a16(8 * tri(n_str)) + 8 * (256 + 256 + 16 + 16 + 16) + 4 * 16 + 8 * 32 + 4 * 16 + 16 + 8 * 16 * 24;
 }
-__host__ __device__ inline int64_t et_slice_bytes(int k, int n_str, int elem) {
-  const int64_t np = (int64_t)k * (k + 1) / 2;
-  const int64_t nbp = ((int64_t)n_str + 15) / 16 * 16;
-  return a16(np * nbp * elem);
+// E slice of one wave, transposed: E[a][P] for one column, 16-string tiles
+// of the longest column by an odd row stride of at least 17 (npair | 1), and
+// a spare tail for the padding rows of the last MFMA tile.  With a stride of
+// at least 16 the padding rows P >= npair of the last row tile reach only
+// into the first 16 (MT - 1) entries of the next string's row.
+__host__ __device__ constexpr int slice_rows(int k) { return (max_strings(k) + 15) / 16 * 16; }
+__host__ __device__ constexpr int slice_stride(int k) {
+  return ((k * (k + 1) / 2) | 1) > 17 ? ((k * (k + 1) / 2) | 1) : 17;
+}
+__host__ __device__ inline int64_t et_slice_bytes(int k, int, int elem) {
+  return a16(((int64_t)slice_rows(k) * slice_stride(k) + 16) * elem);
 }
 
 __device__ inline Lds carve(char* base, const IncDev& d, int lds_bytes) {
   Lds L;
   char* p = base;
   const int n = d.n_str, np = d.npair, k = d.k;
+  L.root = base;
+  L.colb = p;
+  p += colb_bytes(n);
   L.ptab = (int32_t*)p;
   p += ptab_bytes(k, n);
   (void)np;
@@ -152,8 +174,9 @@ __device__ __forceinline__ int pk32(int x, int y) {
 }
 
 // ---------------------------------------------------------------------------
-// Sigma of the packed CI vector in L.cp (unscaled, type T stored in the
-// double slots), accumulated into L.sp (packed, scaled, must be zero).
+// Sigma of the CI vector in L.cp (unscaled; FP32 full (n+1) x (n+1) with a
+// zero last row and column, FP64 packed with a zero tail), accumulated into
+// L.sp (packed, scaled, must be zero).
 // V holds the pair contraction matrix; shift is subtracted from its
 // (diagonal pair, diagonal pair) block, which subtracts shift * N / N^2 * N
 // = shift from the operator.
@@ -194,85 +217,195 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
       }
   }
   if (wave >= et_waves) return;
-  const int nt_count = (n + 15) / 16;
-  const int nbp = nt_count * 16;
-  T* et = (T*)(L.et + (size_t)wave * et_slice_bytes(K, n, (int)sizeof(T)));
-  const int kq = lane >> 4, col = lane & 15;
-  constexpr bool kFull = sizeof(T) == 4;  // FP32: full (n+1)^2 layout, FP64: packed
-  const int ld = n + 1;
-
   constexpr int NPp = 4 * KS;
-  const int16_t* ptA = (const int16_t*)L.ptab;    // [a][Q]: J (n + 1) | neg << 15
-  const int16_t* ptB = ptA + (n + 1) * NPp;       // [a][Q]: J | neg << 15
+  constexpr int NTM = slice_rows(K) / 16;  // 16-string tiles of the longest column
+  constexpr int NS = slice_stride(K);      // E slice row stride (odd, >= 17)
+  static_assert(NS >= 16 && 16 * MT - NS <= NS, "padding rows must stay within the next row's first tiles");
+  constexpr bool kFull = sizeof(T) == 4;   // FP32: full layout, FP64: packed
+  const int nt_count = (n + 15) / 16;
+  const int kq = lane >> 4, col = lane & 15;
+  const int ld = n + 1;
+  T* et = (T*)(L.et + (size_t)wave * et_slice_bytes(K, n, (int)sizeof(T)));
+  const int16_t* pt = (const int16_t*)L.ptab;  // [a][Q]: J | neg << 15, J = n: none
+  T* colb = (T*)L.colb + (size_t)wave * 2 * ld;
+  const uint32_t colb_off = (uint32_t)((const char*)colb - L.root);
+  const uint32_t cp_off = (uint32_t)((const char*)cp - L.root);
 
-  // B operand of one MFMA step: D[Q][(a, b)] = sign1 c[J1][b] + sign2 c[a][J2]
-  // for Q = 4 s + kq.  A missing link, a padding pair and the sentinel row
-  // (a >= n) all carry J = n, which addresses zeros (the zero row / column of
-  // the full layout, the zero tail of the packed one): every load is
-  // unconditional and there is no branch.
-  auto bval = [&](int ar, int arow, int s, int e2, int b) -> T {
-    const int e1 = ptA[arow + 4 * s + kq];
-    T v1, v2;
-    if (kFull) {
-      v1 = cp[(e1 & 0x7FFF) + b];
-      v2 = cp[ar * ld + (e2 & 0x7FFF)];
-    } else {
-      v1 = cp[pk32(ptB[arow + 4 * s + kq] & 0x7FFF, b)];
-      v2 = cp[pk32(ar, e2 & 0x7FFF)];
-    }
-    return ((e1 & 0x8000) ? -v1 : v1) + ((e2 & 0x8000) ? -v2 : v2);
-  };
-
-  for (int b = wave; b < n; b += et_waves) {
-    // beta-part entries of column b, one per k-step of this lane
-    int jb[KS];
+  // B operand of the MFMA step s of tile t for this lane (a = 16 t + col,
+  // Q = 4 s + kq):  D[Q][(a, b)] = sign1 C[J1][b] + sign2 C[a][J2].
+  // The alpha part reads the wave's copy of column b and of its negation
+  // (colb[J1 + neg (n+1)]); its LDS byte offsets depend on (a, Q) only, so
+  // they are computed once per sigma and kept in registers, two 16-bit
+  // offsets a register.  A missing link, a padding pair and a string a >= n
+  // address colb[n] = 0.  The beta part reads C[a][J2] = C[J2][a] with the
+  // sign of (b, Q) applied in a fused multiply-add; J2 = n (no link) reads
+  // the zero row (FP32) or the zero tail (FP64).  No load depends on another.
+  constexpr int NA = NTM * KS;
+  uint32_t ia[(NA + 1) / 2];
+#pragma unroll
+  for (int i = 0; i < (NA + 1) / 2; ++i) ia[i] = 0;
+#pragma unroll
+  for (int t = 0; t < NTM; ++t)
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      const int Q = 4 * s + kq;
-      jb[s] = (int)(uint16_t)ptB[b * NPp + Q];
+      const int a = min(16 * t + col, n);
+      const int e = (int)(uint16_t)pt[a * NPp + 4 * s + kq];
+      const int J = e & 0x7FFF;
+      const int j = J >= n ? n : J + (e >> 15) * ld;
+      const int i = t * KS + s;
+      ia[i >> 1] |= (colb_off + (uint32_t)j * (uint32_t)sizeof(T)) << (16 * (i & 1));
     }
-    // two 16-determinant tiles at a time: six independent MFMA chains
-    for (int nt = 0; nt < nt_count; nt += 2) {
-      const int a0 = min(nt * 16 + col, n), a1 = min(nt * 16 + 16 + col, n);  // n: sentinel
-      const int r0 = a0 * NPp, r1 = a1 * NPp;
+
+  // Alpha-gather links of this lane's strings a = lane + 64 p: two 16-bit
+  // codes per register, each the E-slice offset J NS + Q (below 2^14) with
+  // bit 14 = no link and bit 15 = negative sign, so that the gather issues
+  // all its LDS loads at once.  FP32 keeps them in registers for every
+  // column; FP64 has no registers to spare and decodes them per column.
+  constexpr int LM = ((K + 1) / 2) * ((K + 2) / 2);  // max of na (K - na + 1)
+  constexpr int LP = (LM + 1) / 2;
+  constexpr int NPASS = (max_strings(K) + 63) / 64;
+  constexpr bool kLinkRegs = kFull;
+  auto link_codes = [&](uint32_t (&lk)[NPASS][LP]) {
+#pragma unroll
+    for (int p = 0; p < NPASS; ++p) {
+      const int a = lane + 64 * p;
+#pragma unroll
+      for (int i = 0; i < LP; ++i) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int l = 2 * i + h;
+          uint32_t c = 0x4000u;
+          if (a < n && l < nlink) {
+            const int code = L.links[a * nlink + l];
+            c = (uint32_t)(((code >> 1) & 0xFFFF) * NS + (code >> 17)) | ((uint32_t)(code & 1) << 15);
+          }
+          w |= c << (16 * h);
+        }
+        lk[p][i] = w;
+      }
+    }
+  };
+  uint32_t lk_keep[NPASS][LP];
+  if (kLinkRegs) link_codes(lk_keep);
+
+  // MFMA output row of (lane, r) within a 16-row tile, and the lane's store
+  // base in the transposed slice: E[a][P] at et[a NS + P]
+  T* const ebase = et + col * NS + M::row(kq, 0);
+  constexpr int RSTEP = M::row(0, 1) - M::row(0, 0);  // row step between accumulator registers
+
+  for (int b = wave; b < n; b += et_waves) {
+    // Keep the packed offsets packed: without this the compiler unpacks
+    // them once before the loop into twice as many registers and spills.
+#pragma unroll
+    for (int i = 0; i < (NA + 1) / 2; ++i) asm volatile("" : "+v"(ia[i]));
+    if (kLinkRegs) {
+#pragma unroll
+      for (int p = 0; p < NPASS; ++p)
+#pragma unroll
+        for (int i = 0; i < LP; ++i) asm volatile("" : "+v"(lk_keep[p][i]));
+    }
+    // the wave's copy of column b and its negation (row n / the tail is zero)
+    for (int j = lane; j < ld; j += 64) {
+      const T v = kFull ? cp[j * ld + b] : cp[pk32(j, b)];
+      colb[j] = v;
+      colb[ld + j] = -v;
+    }
+    // beta part of column b, one entry per k-step of this lane
+    int j2[KS];
+    T sg[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int e = (int)(uint16_t)pt[b * NPp + 4 * s + kq];
+      j2[s] = e & 0x7FFF;
+      sg[s] = (e & 0x8000) ? (T)-1 : (T)1;
+    }
+    uint32_t r2[KS];  // FP32: byte offset of C[J2][col]
+#pragma unroll
+    for (int s = 0; s < KS; ++s) r2[s] = cp_off + (uint32_t)((j2[s] * ld + col) * (int)sizeof(T));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    auto beta = [&](int t, int s) -> T {
+      if (kFull) return *(const T*)(L.root + r2[s] + 16 * t * sizeof(T));
+      const int a = min(16 * t + col, n);  // a = n: the zero tail
+      return cp[pk32(a, j2[s])];
+    };
+    // E[:, (a, b)] for one or two 16-string tiles (independent MFMA chains),
+    // stored transposed into the wave's slice.  Rows a >= n of the slice are
+    // padding.  The last MFMA row tile holds rows P >= npair (zero) that
+    // spill into the next string's row: it is stored first, so the other
+    // tiles overwrite what it spilled.
+    auto tiles = [&](auto tt, auto two) {
+      constexpr int t = decltype(tt)::value;
+      constexpr bool kTwo = decltype(two)::value;
       typename M::acc acc0[MT], acc1[MT];
 #pragma unroll
       for (int m = 0; m < MT; ++m) acc0[m] = acc1[m] = M::zero();
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        const T b0 = bval(a0, r0, s, jb[s], b);
-        const T b1 = bval(a1, r1, s, jb[s], b);
+        const int i0 = t * KS + s, i1 = (t + 1) * KS + s;
+        const uint32_t o0 = (ia[i0 >> 1] >> (16 * (i0 & 1))) & 0xFFFFu;
+        const T b0 = fma_t(sg[s], beta(t, s), *(const T*)(L.root + o0));
+        T b1 = (T)0;
+        if (kTwo) {
+          const uint32_t o1 = (ia[i1 >> 1] >> (16 * (i1 & 1))) & 0xFFFFu;
+          b1 = fma_t(sg[s], beta(t + 1, s), *(const T*)(L.root + o1));
+        }
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
           acc0[m] = M::mma(afr[m][s], b0, acc0[m]);
-          acc1[m] = M::mma(afr[m][s], b1, acc1[m]);
+          if (kTwo) acc1[m] = M::mma(afr[m][s], b1, acc1[m]);
         }
       }
 #pragma unroll
-      for (int m = 0; m < MT; ++m)
+      for (int mm = 0; mm < MT; ++mm) {
+        const int m = (mm + MT - 1) % MT;  // last row tile first
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int P = 16 * m + M::row(kq, r);
-          if (m < MT - 1 || P < NP) {
-            et[P * nbp + nt * 16 + col] = acc0[m][r];
-            if (nt + 1 < nt_count) et[P * nbp + nt * 16 + 16 + col] = acc1[m][r];
-          }
+          ebase[16 * t * NS + 16 * m + RSTEP * r] = acc0[m][r];
+          if (kTwo) ebase[16 * (t + 1) * NS + 16 * m + RSTEP * r] = acc1[m][r];
         }
-    }
+        // the overlap is between lanes, which the compiler does not see:
+        // keep the spilling stores ahead of the others
+        if (mm == 0) asm volatile("" ::: "memory");
+      }
+    };
+    static_for<0, (NTM + 1) / 2>([&](auto hp) {
+      constexpr int t = 2 * decltype(hp)::value;
+      if (t + 1 < nt_count)
+        tiles(std::integral_constant<int, t>{}, std::true_type{});
+      else if (t < nt_count)
+        tiles(std::integral_constant<int, t>{}, std::false_type{});
+    });
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int a = lane; a < n; a += 64) {
-      const int32_t* la = L.links + a * nlink;
-      T s = (T)0;
-      for (int l = 0; l < nlink; ++l) {
-        const int code = la[l];
-        const int Q = code >> 17, J = (code >> 1) & 0xFFFF;
-        const T v = et[Q * nbp + J];
-        s += (code & 1) ? -v : v;
+    // S[a][b] = sum over the links (a -> J, pair Q) of sign E[(J, b)][Q]
+    uint32_t lk_col[NPASS][LP];
+    if (!kLinkRegs) link_codes(lk_col);
+    const uint32_t(&lk)[NPASS][LP] = kLinkRegs ? lk_keep : lk_col;
+#pragma unroll
+    for (int p = 0; p < NPASS; ++p) {
+      const int a = lane + 64 * p;
+      T v[2 * LP];
+#pragma unroll
+      for (int i = 0; i < LP; ++i) {
+        v[2 * i] = et[lk[p][i] & 0x3FFFu];
+        v[2 * i + 1] = et[(lk[p][i] >> 16) & 0x3FFFu];
       }
-      const double sc = (a == b) ? 2.0 : kSqrt2;
-      lds_add(&L.sp[pk32(a, b)], sc * (double)s);
+      T s = (T)0;
+#pragma unroll
+      for (int l = 0; l < 2 * LP; ++l) {
+        const uint32_t c = lk[p][l >> 1] >> (16 * (l & 1));
+        T x = (c & 0x8000u) ? -v[l] : v[l];
+        s += (c & 0x4000u) ? (T)0 : x;
+      }
+      if (a < n) {
+        const double sc = (a == b) ? 2.0 : kSqrt2;
+        lds_add(&L.sp[pk32(a, b)], sc * (double)s);
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -280,30 +413,28 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
   }
 }
 
-// Pair tables (decoded, see Lds::ptab) and link lists into LDS.
+// Pair table (decoded, see Lds::ptab) and link lists into LDS.
 __device__ inline void load_tables(const IncDev& d, const Lds& L, const int32_t* __restrict__ tables) {
   const int n = d.n_str, np = d.npair;
   const int npp = npair_pad(d.k);
-  int16_t* ptA = (int16_t*)L.ptab;
-  int16_t* ptB = ptA + (n + 1) * npp;
+  int16_t* pt = (int16_t*)L.ptab;
   for (int i = threadIdx.x; i < (n + 1) * npp; i += blockDim.x) {
     const int a = i / npp, Q = i - a * npp;
     const int e = (a < n && Q < np) ? tables[d.pair_off + a * np + Q] : -1;
     const int J = e < 0 ? n : (e >> 1), neg = e < 0 ? 0 : (e & 1);
-    ptA[i] = (int16_t)(J * (n + 1) | (neg << 15));
-    ptB[i] = (int16_t)(J | (neg << 15));
+    pt[i] = (int16_t)(J | (neg << 15));
   }
   for (int i = threadIdx.x; i < n * d.n_link; i += blockDim.x) L.links[i] = tables[d.link_off + i];
 }
 
-// Expand the packed scaled vector tv into the packed unscaled cp of type T
-// and clear sp.
+// Expand the packed scaled vector tv into the unscaled cp of type T (FP32
+// full with a zero last row and column, FP64 packed with a zero tail) and
+// clear sp.
 template <typename T>
 __device__ inline void prepare_sigma(const IncDev& d, const Lds& L) {
   T* cp = (T*)L.cp;
   const int n = d.n_str, ld = n + 1;
   if (sizeof(T) == 4) {
-    // full symmetric matrix with a zero last row and column
     for (int i = threadIdx.x; i < ld * ld; i += blockDim.x) {
       const int a = i / ld, b = i - a * ld;
       double v = 0.0;
@@ -339,6 +470,8 @@ template <typename T, int K>
 __device__ inline int et_waves_for(const IncDev& d, const Lds& L) {
   const int64_t slice = et_slice_bytes(K, d.n_str, (int)sizeof(T));
   int w = (int)(L.et_total / slice);
+  const int wc = (int)(colb_bytes(d.n_str) / (2 * (int64_t)(d.n_str + 1) * (int64_t)sizeof(T)));
+  w = w < wc ? w : wc;
   const int nw = blockDim.x >> 6;
   return w > nw ? nw : w;
 }

@@ -6,9 +6,30 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "ifci_internal.h"
 
 namespace ifci {
+
+// f(std::integral_constant<int, i>) for i = B .. E-1, unrolled at compile time
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// C(k, k/2): the most strings a k-orbital increment can have
+__host__ __device__ constexpr int max_strings(int k) {
+  int c = 1;
+  for (int i = 1; i <= k / 2; ++i) c = c * (k - k / 2 + i) / i;
+  return c;
+}
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -22,7 +43,7 @@ struct Mfma;
 template <>
 struct Mfma<double> {
   typedef d4 acc;
-  static __device__ __forceinline__ int row(int lane_hi, int r) { return 4 * r + lane_hi; }
+  static constexpr __host__ __device__ int row(int lane_hi, int r) { return 4 * r + lane_hi; }
   static __device__ __forceinline__ acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
   static __device__ __forceinline__ acc mma(double a, double b, acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -31,7 +52,7 @@ struct Mfma<double> {
 template <>
 struct Mfma<float> {
   typedef f4 acc;
-  static __device__ __forceinline__ int row(int lane_hi, int r) { return 4 * lane_hi + r; }
+  static constexpr __host__ __device__ int row(int lane_hi, int r) { return 4 * lane_hi + r; }
   static __device__ __forceinline__ acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
   static __device__ __forceinline__ acc mma(float a, float b, acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);

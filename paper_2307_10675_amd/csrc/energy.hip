@@ -41,32 +41,77 @@ __global__ void eps_kernel(const double* __restrict__ e_inc, const int32_t* __re
   eps[i] = acc.value();
 }
 
+// Compensated pair (s, c): value s + c.  Two pairs combine with an exact
+// two-sum of the leading parts, so the tree below keeps the compensation.
+__device__ inline void two_sum_merge(double& s, double& c, double s2, double c2) {
+  const double t = s + s2;
+  const double bp = t - s;
+  const double err = (s - (t - bp)) + (s2 - bp);
+  s = t;
+  c = c + c2 + err;
+}
+
 // out[0] = E_total, out[1] = E_ref, out[1 + k] = E_c^(k); bad = number of
-// increments whose status is not DONE.
-__global__ void order_sum_kernel(const double* __restrict__ eps, const int32_t* __restrict__ inc_size,
-                                 int n_inc, int order, const double* __restrict__ misc,
-                                 const int32_t* __restrict__ status, double* __restrict__ out,
-                                 int32_t* __restrict__ bad) {
-  __shared__ double sums[64];
-  const int k = threadIdx.x + 1;
-  if (k <= order) {
+// increments whose status is not DONE.  Increments are sorted by size, so
+// order k is one contiguous range; each thread sums a contiguous chunk of it
+// (Neumaier) and the block merges the chunks in a fixed tree.
+constexpr int kSumThreads = 256;
+__global__ void __launch_bounds__(kSumThreads)
+    order_sum_kernel(const double* __restrict__ eps, const int32_t* __restrict__ inc_size, int n_inc, int order,
+                     const double* __restrict__ misc, const int32_t* __restrict__ status,
+                     double* __restrict__ out, int32_t* __restrict__ bad) {
+  __shared__ double ss[kSumThreads], sc[kSumThreads];
+  __shared__ int sb[kSumThreads];
+  const int t = threadIdx.x;
+  Neumaier tot;
+  if (t == 0) tot.add(misc[0]);
+  for (int k = 1; k <= order; ++k) {
+    // first index with size >= k and first with size > k
+    int lo = 0, hi = n_inc;
+    while (lo < hi) {
+      const int m = (lo + hi) >> 1;
+      if (inc_size[m] < k) lo = m + 1; else hi = m;
+    }
+    int lo2 = lo, hi2 = n_inc;
+    while (lo2 < hi2) {
+      const int m = (lo2 + hi2) >> 1;
+      if (inc_size[m] <= k) lo2 = m + 1; else hi2 = m;
+    }
+    const int cnt = lo2 - lo, chunk = (cnt + kSumThreads - 1) / kSumThreads;
     Neumaier acc;
-    for (int i = 0; i < n_inc; ++i)
-      if (inc_size[i] == k) acc.add(eps[i]);
-    sums[k - 1] = acc.value();
+    for (int i = lo + t * chunk; i < lo + min(cnt, (t + 1) * chunk); ++i) acc.add(eps[i]);
+    ss[t] = acc.s;
+    sc[t] = acc.c;
+    __syncthreads();
+    for (int w = kSumThreads / 2; w > 0; w >>= 1) {
+      if (t < w) {
+        double a = ss[t], c = sc[t];
+        two_sum_merge(a, c, ss[t + w], sc[t + w]);
+        ss[t] = a;
+        sc[t] = c;
+      }
+      __syncthreads();
+    }
+    if (t == 0) {
+      const double v = ss[0] + sc[0];
+      out[1 + k] = v;
+      tot.add(v);
+    }
+    __syncthreads();
   }
+  int nb = 0;
+  if (status)
+    for (int i = t; i < n_inc; i += kSumThreads) nb += (status[i] != IFCI_INC_DONE);
+  sb[t] = nb;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    Neumaier tot;
-    tot.add(misc[0]);
-    for (int j = 0; j < order; ++j) tot.add(sums[j]);
+  for (int w = kSumThreads / 2; w > 0; w >>= 1) {
+    if (t < w) sb[t] += sb[t + w];
+    __syncthreads();
+  }
+  if (t == 0) {
     out[0] = tot.value();
     out[1] = misc[0];
-    for (int j = 0; j < order; ++j) out[2 + j] = sums[j];
-    int nb = 0;
-    if (status)
-      for (int i = 0; i < n_inc; ++i) nb += (status[i] != IFCI_INC_DONE);
-    *bad = nb;
+    *bad = sb[0];
   }
 }
 
@@ -76,7 +121,7 @@ hipError_t launch_energy(const double* e_inc, const int32_t* status, const int32
                          hipStream_t st) {
   hipLaunchKernelGGL(eps_kernel, dim3((n_inc + 255) / 256), dim3(256), 0, st, e_inc, sub_ptr, sub_idx,
                      inc_size, n_inc, misc_in, eps);
-  hipLaunchKernelGGL(order_sum_kernel, dim3(1), dim3(64), 0, st, eps, inc_size, n_inc, order, misc_in,
+  hipLaunchKernelGGL(order_sum_kernel, dim3(1), dim3(kSumThreads), 0, st, eps, inc_size, n_inc, order, misc_in,
                      status, out, bad);
   return hipGetLastError();
 }

@@ -12,36 +12,39 @@ from tests.helpers import active_hamiltonian, load_golden
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-9
+# max_space 12: thick-restart Davidson; max_space 3: the {x, w, p} solver
+SPACES = [12, 3]
 
 
 def _check_sha(problem, g):
     assert problem.sha256() == g["sha256"], "synthetic generator changed; regenerate tests/golden"
 
 
+@pytest.mark.parametrize("space", SPACES)
 @pytest.mark.parametrize("rep", range(10))
-def test_workload0_fp64_davidson(rep):
+def test_workload0_fp64_davidson(rep, space):
     """6 orbitals / 6 electrons: lowest even-spin root to residual 1e-10."""
     import torch
     p = synthetic.workload(0, rep)
     g = load_golden(f"w0_r{rep}")
     _check_sha(p, g)
-    print(f"[solve] workload 0 replicate {rep}", flush=True)
-    plan, res = ifci.solve(p, r_tol=1e-10)
+    print(f"[solve] workload 0 replicate {rep} max_space {space}", flush=True)
+    plan, res = ifci.solve(p, r_tol=1e-10, max_space=space, max_iter=500)
     torch.cuda.synchronize()
     assert int(res["status"][0]) == ifci.INC_DONE
     assert float(res["resid"][0]) <= 1e-10
     assert abs(float(res["E"][0]) - g["increments"][0]["E"]) <= TOL64
 
 
-@pytest.mark.parametrize("solver", [ifci.BATCHED, ifci.PLAIN])
-def test_workload1_all_increments(solver):
+@pytest.mark.parametrize("solver,space", [(ifci.BATCHED, 12), (ifci.BATCHED, 3), (ifci.PLAIN, 12)])
+def test_workload1_all_increments(solver, space):
     """10 bodies, order 3: all 175 increments, eps_S and the total."""
     import torch
     p = synthetic.workload(1)
     g = load_golden("w1")
     _check_sha(p, g)
-    print(f"[solve] workload 1 solver {solver}", flush=True)
-    plan, res = ifci.solve(p, solver=solver, r_tol=1e-8)
+    print(f"[solve] workload 1 solver {solver} max_space {space}", flush=True)
+    plan, res = ifci.solve(p, solver=solver, r_tol=1e-8, max_space=space, max_iter=500)
     torch.cuda.synchronize()
     E = res["E"].cpu().numpy()
     st = res["status"].cpu().numpy()
@@ -58,13 +61,14 @@ def test_workload1_all_increments(solver):
     assert abs(res["total"] - g["total"]) <= 1e-8
 
 
-def test_full_order_identity():
+@pytest.mark.parametrize("space", SPACES)
+def test_full_order_identity(space):
     """Four bodies to full order: the expansion total equals the 8o8e FCI energy."""
     import torch
     p = synthetic.chain(4, seed=1100, order=4)
     g = load_golden("chain4_full")
     _check_sha(p, g)
-    plan, res = ifci.solve(p, r_tol=1e-9)
+    plan, res = ifci.solve(p, r_tol=1e-9, max_space=space, max_iter=500)
     torch.cuda.synchronize()
     E = res["E"].cpu().numpy()
     assert np.abs(E - np.array([x["E"] for x in g["increments"]])).max() <= TOL64
@@ -72,17 +76,19 @@ def test_full_order_identity():
     assert abs(res["total"] - g["total"]) <= 1e-9
 
 
-def test_workload2_sample_fp64_and_mixed():
+@pytest.mark.parametrize("space", SPACES)
+def test_workload2_sample_fp64_and_mixed(space):
     """16 bodies, order 4 (2516 increments): FP64 at 1e-9 and mixed at 1e-6
     on the oracle sample; mixed vs FP64 on every increment at 1e-6."""
     import torch
     p = synthetic.workload(2)
     g = load_golden("w2_sample")
     _check_sha(p, g)
-    print("[solve] workload 2 fp64", flush=True)
-    plan64, r64 = ifci.solve(p, r_tol=1e-7, max_iter=300)
-    print("[solve] workload 2 mixed", flush=True)
-    plan32, r32 = ifci.solve(p, precision=ifci.MIXED, r_tol=3e-5, r_tol_inner=1e-5, max_iter=300)
+    print(f"[solve] workload 2 fp64 max_space {space}", flush=True)
+    plan64, r64 = ifci.solve(p, r_tol=1e-7, max_iter=500, max_space=space)
+    print(f"[solve] workload 2 mixed max_space {space}", flush=True)
+    plan32, r32 = ifci.solve(p, precision=ifci.MIXED, r_tol=3e-5, r_tol_inner=1e-5, max_iter=500,
+                             max_space=space)
     torch.cuda.synchronize()
     incs = [i.bodies for i in plan64.increments()]
     E64 = r64["E"].cpu().numpy()
@@ -96,12 +102,13 @@ def test_workload2_sample_fp64_and_mixed():
     assert np.abs(E32 - E64).max() <= 1e-6
 
 
-def test_mixed_uses_fp32_stage_and_refines():
-    """Mixed precision runs FP32 sigma first: its iteration count differs from FP64."""
+@pytest.mark.parametrize("space", SPACES)
+def test_mixed_uses_fp32_stage_and_refines(space):
+    """Mixed precision: FP32 sigma stage, then FP64 refinement to 1e-9 Eh."""
     import torch
     p = synthetic.workload(0, 3)
     g = load_golden("w0_r3")
-    plan, res = ifci.solve(p, precision=ifci.MIXED, r_tol=1e-7, r_tol_inner=1e-5)
+    plan, res = ifci.solve(p, precision=ifci.MIXED, r_tol=1e-7, r_tol_inner=1e-5, max_space=space, max_iter=500)
     torch.cuda.synchronize()
     assert int(res["status"][0]) == ifci.INC_DONE
     assert abs(float(res["E"][0]) - g["increments"][0]["E"]) <= 1e-9
@@ -124,16 +131,17 @@ def test_vector_matches_oracle():
         assert np.abs(C - C.T).max() == 0.0
 
 
-def test_eviction_requeue_bitwise():
+@pytest.mark.parametrize("space", SPACES)
+def test_eviction_requeue_bitwise(space):
     """Failure injection: evicted increments report EVICTED; solving them
     again gives bitwise the energies of an undisturbed run."""
     import torch
     p = synthetic.workload(1)
-    plan, clean = ifci.solve(p, r_tol=1e-8)
+    plan, clean = ifci.solve(p, r_tol=1e-8, max_space=space, max_iter=500)
     n = plan.n_inc
     mask = np.zeros(n, dtype=np.uint8)
     mask[::7] = 1
-    plan2 = ifci.Plan(p, r_tol=1e-8).attach(p.h, p.eri)
+    plan2 = ifci.Plan(p, r_tol=1e-8, max_space=space, max_iter=500).attach(p.h, p.eri)
     e, st, it, rs = plan2.davidson(evict=mask)
     st = st.cpu().numpy()
     assert (st[mask == 1] == ifci.INC_EVICTED).all()
@@ -158,11 +166,12 @@ def test_not_converged_status():
     assert en["converged"] is False
 
 
-def test_deterministic_bitwise():
+@pytest.mark.parametrize("space", SPACES)
+def test_deterministic_bitwise(space):
     import torch
     p = synthetic.workload(1)
-    _, a = ifci.solve(p, r_tol=1e-8)
-    _, b = ifci.solve(p, r_tol=1e-8)
+    _, a = ifci.solve(p, r_tol=1e-8, max_space=space, max_iter=500)
+    _, b = ifci.solve(p, r_tol=1e-8, max_space=space, max_iter=500)
     assert np.array_equal(a["E"].cpu().numpy(), b["E"].cpu().numpy())
     assert a["total"] == b["total"]
 
