@@ -67,7 +67,9 @@ typedef enum {
 
 typedef enum {
   IFCI_SOLVER_BATCHED = 0, /* one persistent workgroup per increment, whole
-                              Davidson on chip; increments up to 12 orbitals */
+                              eigensolve on chip, increments of at most 8
+                              active orbitals (larger ones take the plain
+                              path inside the same call) */
   IFCI_SOLVER_PLAIN = 1    /* per increment, device-wide kernels for sigma and
                               vector steps, host-driven loop; any size */
 } ifci_solver;
@@ -97,8 +99,11 @@ typedef struct {
   int32_t solver;     /* ifci_solver */
   double r_tol;       /* converged when ||H c - E c|| <= r_tol (unit c, FP64) */
   double r_tol_inner; /* IFCI_MIXED: FP32 stage stops at this residual */
-  int32_t max_iter;   /* Davidson iterations (sigma builds) per increment */
-  int32_t max_space;  /* subspace size before restart, 2..16 */
+  int32_t max_iter;   /* eigensolver iterations (sigma builds) per increment */
+  int32_t max_space;  /* Davidson subspace size before a thick restart,
+                         2..16; in the batched solver 3 selects the
+                         three-vector {x, w, p} iteration (locally
+                         optimal, no restarts) */
   uint32_t flags;     /* reserved, 0 */
 } ifci_options;
 

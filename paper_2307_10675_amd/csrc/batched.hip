@@ -108,8 +108,9 @@ __host__ __device__ constexpr int slice_rows(int k) { return (max_strings(k) + 1
 __host__ __device__ constexpr int slice_stride(int k) {
   return ((k * (k + 1) / 2) | 1) > 17 ? ((k * (k + 1) / 2) | 1) : 17;
 }
+// Entry rows * stride + 16 is kept zero: absent links read it.
 __host__ __device__ inline int64_t et_slice_bytes(int k, int, int elem) {
-  return a16(((int64_t)slice_rows(k) * slice_stride(k) + 16) * elem);
+  return a16(((int64_t)slice_rows(k) * slice_stride(k) + 17) * elem);
 }
 
 __device__ inline Lds carve(char* base, const IncDev& d, int lds_bytes) {
@@ -256,43 +257,69 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
       ia[i >> 1] |= (colb_off + (uint32_t)j * (uint32_t)sizeof(T)) << (16 * (i & 1));
     }
 
-  // Alpha-gather links of this lane's strings a = lane + 64 p: two 16-bit
-  // codes per register, each the E-slice offset J NS + Q (below 2^14) with
-  // bit 14 = no link and bit 15 = negative sign, so that the gather issues
-  // all its LDS loads at once.  FP32 keeps them in registers for every
-  // column; FP64 has no registers to spare and decodes them per column.
+  // Alpha-gather link codes, two 16-bit codes per register: the E-slice
+  // offset J NS + Q (below 2^15) with bit 15 = negative sign; an absent link
+  // reads the slice's zero entry.  Pass 0: string a = lane, all its links.
+  // Pass 1 (more than 64 strings, 8 orbitals): strings 64 + lane / 8, three
+  // links per lane, summed over the 8 lanes of a string in a fixed tree.
+  // FP32 keeps the codes in registers for every column; FP64 has no
+  // registers to spare and decodes them per column.
   constexpr int LM = ((K + 1) / 2) * ((K + 2) / 2);  // max of na (K - na + 1)
   constexpr int LP = (LM + 1) / 2;
-  constexpr int NPASS = (max_strings(K) + 63) / 64;
+  constexpr bool kTwoPass = max_strings(K) > 64;
+  static_assert(!kTwoPass || (LM <= 24 && max_strings(K) <= 64 + 8), "pass 1 covers 8 strings of 24 links");
+  constexpr int ZI = slice_rows(K) * NS + 16;  // zero entry of the slice
   constexpr bool kLinkRegs = kFull;
-  auto link_codes = [&](uint32_t (&lk)[NPASS][LP]) {
+  auto code_of = [&](int a, int l) -> uint32_t {
+    if (a < n && l < nlink) {
+      const int code = L.links[a * nlink + l];
+      return (uint32_t)(((code >> 1) & 0xFFFF) * NS + (code >> 17)) | ((uint32_t)(code & 1) << 15);
+    }
+    return (uint32_t)ZI;
+  };
+  const int a1 = 64 + (lane >> 3);  // pass-1 string of this lane
+  auto link_codes = [&](uint32_t (&lk0)[LP], uint32_t (&lk1)[2]) {
 #pragma unroll
-    for (int p = 0; p < NPASS; ++p) {
-      const int a = lane + 64 * p;
-#pragma unroll
-      for (int i = 0; i < LP; ++i) {
-        uint32_t w = 0;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int l = 2 * i + h;
-          uint32_t c = 0x4000u;
-          if (a < n && l < nlink) {
-            const int code = L.links[a * nlink + l];
-            c = (uint32_t)(((code >> 1) & 0xFFFF) * NS + (code >> 17)) | ((uint32_t)(code & 1) << 15);
-          }
-          w |= c << (16 * h);
-        }
-        lk[p][i] = w;
-      }
+    for (int i = 0; i < LP; ++i) lk0[i] = code_of(lane, 2 * i) | (code_of(lane, 2 * i + 1) << 16);
+    if (kTwoPass) {
+      const int l1 = 3 * (lane & 7);
+      lk1[0] = code_of(a1, l1) | (code_of(a1, l1 + 1) << 16);
+      lk1[1] = code_of(a1, l1 + 2);
     }
   };
-  uint32_t lk_keep[NPASS][LP];
-  if (kLinkRegs) link_codes(lk_keep);
+  uint32_t lk0_keep[LP], lk1_keep[2];
+  if (kLinkRegs) link_codes(lk0_keep, lk1_keep);
+  if (lane == 0) et[ZI] = (T)0;
 
   // MFMA output row of (lane, r) within a 16-row tile, and the lane's store
   // base in the transposed slice: E[a][P] at et[a NS + P]
   T* const ebase = et + col * NS + M::row(kq, 0);
   constexpr int RSTEP = M::row(0, 1) - M::row(0, 0);  // row step between accumulator registers
+
+  // per column: the wave's copy of column b and its negation (row n / the
+  // tail is zero), and the beta part (one entry per k-step of this lane).
+  // The next column's are prepared while the current one is gathered.
+  int j2[KS];
+  T sg[KS];
+  uint32_t r2[KS];  // FP32: byte offset of C[J2][col]
+  auto column_setup = [&](int bb) {
+    for (int j = lane; j < ld; j += 64) {
+      const T v = kFull ? cp[j * ld + bb] : cp[pk32(j, bb)];
+      colb[j] = v;
+      colb[ld + j] = -v;
+    }
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int e = (int)(uint16_t)pt[bb * NPp + 4 * s + kq];
+      j2[s] = e & 0x7FFF;
+      sg[s] = (e & 0x8000) ? (T)-1 : (T)1;
+      r2[s] = cp_off + (uint32_t)((j2[s] * ld + col) * (int)sizeof(T));
+    }
+  };
+  if (wave < n) column_setup(wave);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
   for (int b = wave; b < n; b += et_waves) {
     // Keep the packed offsets packed: without this the compiler unpacks
@@ -301,31 +328,8 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
     for (int i = 0; i < (NA + 1) / 2; ++i) asm volatile("" : "+v"(ia[i]));
     if (kLinkRegs) {
 #pragma unroll
-      for (int p = 0; p < NPASS; ++p)
-#pragma unroll
-        for (int i = 0; i < LP; ++i) asm volatile("" : "+v"(lk_keep[p][i]));
+      for (int i = 0; i < LP; ++i) asm volatile("" : "+v"(lk0_keep[i]));
     }
-    // the wave's copy of column b and its negation (row n / the tail is zero)
-    for (int j = lane; j < ld; j += 64) {
-      const T v = kFull ? cp[j * ld + b] : cp[pk32(j, b)];
-      colb[j] = v;
-      colb[ld + j] = -v;
-    }
-    // beta part of column b, one entry per k-step of this lane
-    int j2[KS];
-    T sg[KS];
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const int e = (int)(uint16_t)pt[b * NPp + 4 * s + kq];
-      j2[s] = e & 0x7FFF;
-      sg[s] = (e & 0x8000) ? (T)-1 : (T)1;
-    }
-    uint32_t r2[KS];  // FP32: byte offset of C[J2][col]
-#pragma unroll
-    for (int s = 0; s < KS; ++s) r2[s] = cp_off + (uint32_t)((j2[s] * ld + col) * (int)sizeof(T));
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
     auto beta = [&](int t, int s) -> T {
       if (kFull) return *(const T*)(L.root + r2[s] + 16 * t * sizeof(T));
@@ -343,21 +347,35 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
       typename M::acc acc0[MT], acc1[MT];
 #pragma unroll
       for (int m = 0; m < MT; ++m) acc0[m] = acc1[m] = M::zero();
+      auto alpha = [&](int tt2, int s) -> T {
+        const int i = tt2 * KS + s;
+        return *(const T*)(L.root + ((ia[i >> 1] >> (16 * (i & 1))) & 0xFFFFu));
+      };
+      // loads of step s + 1 are issued ahead of the MFMAs of step s
+      T va0 = alpha(t, 0), vb0 = beta(t, 0), va1 = (T)0, vb1 = (T)0;
+      if (kTwo) {
+        va1 = alpha(t + 1, 0);
+        vb1 = beta(t + 1, 0);
+      }
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        const int i0 = t * KS + s, i1 = (t + 1) * KS + s;
-        const uint32_t o0 = (ia[i0 >> 1] >> (16 * (i0 & 1))) & 0xFFFFu;
-        const T b0 = fma_t(sg[s], beta(t, s), *(const T*)(L.root + o0));
-        T b1 = (T)0;
-        if (kTwo) {
-          const uint32_t o1 = (ia[i1 >> 1] >> (16 * (i1 & 1))) & 0xFFFFu;
-          b1 = fma_t(sg[s], beta(t + 1, s), *(const T*)(L.root + o1));
+        const T b0 = fma_t(sg[s], vb0, va0);
+        const T b1 = kTwo ? fma_t(sg[s], vb1, va1) : (T)0;
+        if (s + 1 < KS) {
+          va0 = alpha(t, s + 1);
+          vb0 = beta(t, s + 1);
+          if (kTwo) {
+            va1 = alpha(t + 1, s + 1);
+            vb1 = beta(t + 1, s + 1);
+          }
         }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
           acc0[m] = M::mma(afr[m][s], b0, acc0[m]);
           if (kTwo) acc1[m] = M::mma(afr[m][s], b1, acc1[m]);
         }
+        __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int mm = 0; mm < MT; ++mm) {
@@ -382,30 +400,37 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // the next column's copy and beta part (colb and r2 are free again)
+    if (b + et_waves < n) column_setup(b + et_waves);
     // S[a][b] = sum over the links (a -> J, pair Q) of sign E[(J, b)][Q]
-    uint32_t lk_col[NPASS][LP];
-    if (!kLinkRegs) link_codes(lk_col);
-    const uint32_t(&lk)[NPASS][LP] = kLinkRegs ? lk_keep : lk_col;
-#pragma unroll
-    for (int p = 0; p < NPASS; ++p) {
-      const int a = lane + 64 * p;
+    uint32_t lk0_col[LP], lk1_col[2];
+    if (!kLinkRegs) link_codes(lk0_col, lk1_col);
+    const uint32_t(&lk0)[LP] = kLinkRegs ? lk0_keep : lk0_col;
+    const uint32_t(&lk1)[2] = kLinkRegs ? lk1_keep : lk1_col;
+    {
       T v[2 * LP];
 #pragma unroll
       for (int i = 0; i < LP; ++i) {
-        v[2 * i] = et[lk[p][i] & 0x3FFFu];
-        v[2 * i + 1] = et[(lk[p][i] >> 16) & 0x3FFFu];
+        v[2 * i] = et[lk0[i] & 0x7FFFu];
+        v[2 * i + 1] = et[(lk0[i] >> 16) & 0x7FFFu];
       }
-      T s = (T)0;
+      // all loads in flight before the first use (left alone, the compiler
+      // trades them for registers and waits on each load in turn)
+      __builtin_amdgcn_sched_barrier(0);
+      T sum = (T)0;
 #pragma unroll
-      for (int l = 0; l < 2 * LP; ++l) {
-        const uint32_t c = lk[p][l >> 1] >> (16 * (l & 1));
-        T x = (c & 0x8000u) ? -v[l] : v[l];
-        s += (c & 0x4000u) ? (T)0 : x;
-      }
-      if (a < n) {
-        const double sc = (a == b) ? 2.0 : kSqrt2;
-        lds_add(&L.sp[pk32(a, b)], sc * (double)s);
-      }
+      for (int l = 0; l < 2 * LP; ++l) sum += ((lk0[l >> 1] >> (16 * (l & 1))) & 0x8000u) ? -v[l] : v[l];
+      if (lane < n) lds_add(&L.sp[pk32(lane, b)], (lane == b ? 2.0 : kSqrt2) * (double)sum);
+    }
+    if (kTwoPass && n > 64) {
+      const T u0 = et[lk1[0] & 0x7FFFu], u1 = et[(lk1[0] >> 16) & 0x7FFFu], u2 = et[lk1[1] & 0x7FFFu];
+      __builtin_amdgcn_sched_barrier(0);
+      T sum = ((lk1[0] & 0x8000u) ? -u0 : u0) + ((lk1[0] & 0x80000000u) ? -u1 : u1);
+      sum += (lk1[1] & 0x8000u) ? -u2 : u2;
+      sum += __shfl_down(sum, 4);
+      sum += __shfl_down(sum, 2);
+      sum += __shfl_down(sum, 1);
+      if ((lane & 7) == 0 && a1 < n) lds_add(&L.sp[pk32(a1, b)], (a1 == b ? 2.0 : kSqrt2) * (double)sum);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -434,27 +459,27 @@ template <typename T>
 __device__ inline void prepare_sigma(const IncDev& d, const Lds& L) {
   T* cp = (T*)L.cp;
   const int n = d.n_str, ld = n + 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   if (sizeof(T) == 4) {
-    for (int i = threadIdx.x; i < ld * ld; i += blockDim.x) {
-      const int a = i / ld, b = i - a * ld;
-      double v = 0.0;
-      if (a < n && b < n) {
-        v = L.tv[pk32(a, b)];
-        if (a != b) v *= kRSqrt2;
+    for (int a = wave; a < ld; a += nw)
+      for (int b = lane; b < ld; b += 64) {
+        double v = 0.0;
+        if (a < n && b < n) {
+          v = L.tv[pk32(a, b)];
+          if (a != b) v *= kRSqrt2;
+        }
+        cp[a * ld + b] = (T)v;
       }
-      cp[i] = (T)v;
-    }
-    for (int64_t i = threadIdx.x; i < d.n_sym; i += blockDim.x) L.sp[i] = 0.0;
   } else {
-    for (int64_t i = threadIdx.x; i < d.n_sym; i += blockDim.x) {
-      int a, b;
-      unpack(i, &a, &b);
-      const double v = L.tv[i];
-      cp[i] = (T)(a == b ? v : v * kRSqrt2);
-      L.sp[i] = 0.0;
-    }
+    for (int b = wave; b < n; b += nw)
+      for (int a = lane; a <= b; a += 64) {
+        const int i = ((b * (b + 1)) >> 1) + a;
+        const double v = L.tv[i];
+        cp[i] = (T)(a == b ? v : v * kRSqrt2);
+      }
     for (int i = threadIdx.x; i <= n; i += blockDim.x) cp[d.n_sym + i] = (T)0;  // zero tail
   }
+  for (int64_t i = threadIdx.x; i < d.n_sym; i += blockDim.x) L.sp[i] = 0.0;
   __syncthreads();
 }
 
@@ -857,13 +882,16 @@ __device__ inline void small_eig3(double g[3][3], double* theta, double z[3]) {
   double v[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
 #pragma unroll 1
   for (int sweep = 0; sweep < 16; ++sweep) {
-    // per-pair test: a decoupled sentinel row must not mask the others
+    // per-pair test: a decoupled sentinel row must not mask the others.
+    // Rotations below 1e-15 of the pair's diagonal are skipped: they would
+    // move the eigenvalue by ~1e-30 relative, while FP64 rounding keeps
+    // regenerating off-diagonal noise near 1e-16 that must not be chased.
     bool rotated = false;
 #pragma unroll
     for (int pq = 0; pq < 3; ++pq) {
       const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
       const double apq = g[p][q];
-      if (fabs(apq) > 1e-17 * (fabs(g[p][p]) + fabs(g[q][q])) && fabs(apq) > 1e-300) {
+      if (fabs(apq) > 1e-15 * (fabs(g[p][p]) + fabs(g[q][q])) && fabs(apq) > 1e-300) {
         rotated = true;
         const double tau = (g[q][q] - g[p][p]) / (2.0 * apq);
         const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
@@ -927,7 +955,6 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
   double* wv = base + st;
   double* pv = base + 2 * st;
   double* ax = base + mmax * st;
-  double* aw = ax + st;
   double* ap = ax + 2 * st;
   double* HD = base + 2 * mmax * st;
   double* X = HD + st;
@@ -956,6 +983,10 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
   __syncthreads();
   IFCI_MARK(kPhPrologue);
 
+  // vector entries per thread: the packed sector of the largest K-orbital shape
+  constexpr int NE = (max_strings(K) * (max_strings(K) + 1) / 2 + kBatchThreads - 1) / kBatchThreads;
+  // every vector of the increment addressed from `base` by a 32-bit offset
+  const int nsi = (int)ns, sti = (int)st, mst = mmax * (int)st;
   const int ew64 = et_waves_for<double, K>(d, L);
   const int ew32 = et_waves_for<float, K>(d, L);
   int phase = (A.precision == IFCI_MIXED) ? 32 : 64;
@@ -975,35 +1006,64 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
       sigma_phase<double, K>(d, L, Vm, E0, ew64);
     ++iters;
     IFCI_MARK(kPhSigma);
+    // ---- this thread's NE entries of x, w, p, Ax, Ap and the diagonal, in
+    // registers for the whole non-sigma part of the iteration (one round of
+    // loads; sigma(w) is read from L.sp)
+    // (32-bit indices clamped into range: every load is unconditional and
+    // addressed from a uniform base; entries past ns are zeroed after)
+    double rx[NE], rw[NE], rp[NE], rax[NE], rap[NE], rhd[NE], rs[NE];
+    const bool use_w = !fresh, use_p = !fresh && have_p;
+    // an opaque copy of the thread index: the element addresses are then
+    // formed here, not hoisted out of the iteration loop into (spilled)
+    // registers
+    int tix = tid;
+    asm volatile("" : "+v"(tix));
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int i = min(tix + e * kBatchThreads, nsi - 1);
+      rx[e] = base[i];
+      rw[e] = base[sti + i];
+      rp[e] = base[2 * sti + i];
+      rax[e] = base[mst + i];
+      rap[e] = base[mst + 2 * sti + i];
+      rhd[e] = base[2 * mst + i];
+      rs[e] = L.sp[i];
+    }
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const bool in = tid + e * kBatchThreads < nsi;
+      if (!in) rx[e] = rs[e] = rhd[e] = 0.0;
+      if (!in || !use_w) rw[e] = rax[e] = 0.0;
+      if (!in || !use_p) rp[e] = rap[e] = 0.0;
+    }
     double gxw = 0.0, gww = 0.0, gpw = 0.0;
     if (fresh) {
-      // ax = sigma(x), theta = x.Ax
+      // Ax = sigma(x), theta = x.Ax
       double acc[1] = {0.0};
-      for (int64_t i = tid; i < ns; i += blockDim.x) {
-        const double s = L.sp[i];
-        ax[i] = s;
-        acc[0] += xv[i] * s;
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        rax[e] = rs[e];
+        acc[0] += rx[e] * rs[e];
       }
       block_sum<1>(acc, L.red, L.scal);
       theta = L.scal[0];
       have_p = false;
     } else {
-      // aw = sigma(w) and the new column of the 3 x 3 Rayleigh-Ritz matrix
+      // the new column of the 3 x 3 Rayleigh-Ritz matrix
       double acc[3] = {0.0, 0.0, 0.0};
-      for (int64_t i = tid; i < ns; i += blockDim.x) {
-        const double s = L.sp[i];
-        aw[i] = s;
-        acc[0] += xv[i] * s;
-        acc[1] += wv[i] * s;
-        if (have_p) acc[2] += pv[i] * s;
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        acc[0] += rx[e] * rs[e];
+        acc[1] += rw[e] * rs[e];
+        acc[2] += rp[e] * rs[e];
       }
       block_sum<3>(acc, L.red, L.scal);
       gxw = L.scal[0];
       gww = L.scal[1];
-      gpw = L.scal[2];
+      gpw = have_p ? L.scal[2] : 0.0;
     }
     IFCI_MARK(kPhSubspace);
-    // ---- Rayleigh-Ritz on span{x, w, p} and the update pass
+    // ---- Rayleigh-Ritz on span{x, w, p}
     double cx[3] = {1.0, 0.0, 0.0}, cpv[3] = {0.0, 0.0, 0.0};
     bool new_p = false;
     if (!fresh) {
@@ -1035,14 +1095,10 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
       }
       // x'.Ap'' and p''.Ap'' from the 3 x 3 matrix (g was overwritten)
       const double G3[3][3] = {{theta, gxw, xap}, {gxw, gww, gpw}, {xap, gpw, pap}};
-      double gx[3], gp[3];
+      double gp[3];
       for (int i = 0; i < 3; ++i) {
-        gx[i] = 0.0;
         gp[i] = 0.0;
-        for (int j = 0; j < 3; ++j) {
-          gx[i] += G3[i][j] * cx[j];
-          gp[i] += G3[i][j] * cpv[j];
-        }
+        for (int j = 0; j < 3; ++j) gp[i] += G3[i][j] * cpv[j];
       }
       double nxap = 0.0, npap = 0.0;
       for (int i = 0; i < 3; ++i) {
@@ -1053,46 +1109,60 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
       xap = nxap;
       pap = npap;
     }
-    // update x, ax, p, ap in place; residual r = ax - theta x; correction
-    // w = r / (theta - (H_II - E0)) into LDS with its overlaps with x', p'
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int64_t i = tid; i < ns; i += blockDim.x) {
-      double x = xv[i], sx = ax[i];
-      double pnew = 0.0, apnew = 0.0;
+    // ---- update x, Ax, p, Ap in registers; residual r = Ax - theta x and
+    // correction t = r / (theta - (H_II - E0)) with its overlaps
+    double rt[NE];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      double x = rx[e], sx = rax[e];
       if (!fresh) {
-        const double w = wv[i], sw = aw[i];
-        const double pp = have_p ? pv[i] : 0.0, sp = have_p ? ap[i] : 0.0;
-        const double xn = cx[0] * x + cx[1] * w + cx[2] * pp;
-        const double sxn = cx[0] * sx + cx[1] * sw + cx[2] * sp;
-        pnew = cpv[0] * x + cpv[1] * w + cpv[2] * pp;
-        apnew = cpv[0] * sx + cpv[1] * sw + cpv[2] * sp;
-        x = xn;
-        sx = sxn;
-        xv[i] = x;
-        ax[i] = sx;
+        const double w = rw[e], sw = rs[e], pp = rp[e], sp = rap[e];
+        x = cx[0] * rx[e] + cx[1] * w + cx[2] * pp;
+        sx = cx[0] * rax[e] + cx[1] * sw + cx[2] * sp;
+        const double pnew = cpv[0] * rx[e] + cpv[1] * w + cpv[2] * pp;
+        const double apnew = cpv[0] * rax[e] + cpv[1] * sw + cpv[2] * sp;
         if (new_p) {
-          pv[i] = pnew;
-          ap[i] = apnew;
+          rp[e] = pnew;
+          rap[e] = apnew;
         }
+        rx[e] = x;
+        rax[e] = sx;
       }
-      const double r = sx - theta * x;
-      double den = theta - (HD[i] - E0);
+      const bool in = tid + e * kBatchThreads < nsi;
+      const double r = in ? sx - theta * x : 0.0;
+      double den = theta - (rhd[e] - E0);
       if (fabs(den) < 1e-8) den = (den < 0.0) ? -1e-8 : 1e-8;
       const double t = r / den;
-      L.tv[i] = t;
+      rt[e] = t;
       acc[0] += r * r;
       acc[1] += t * t;
       acc[2] += x * t;
-      acc[3] += pnew * t;
+      acc[3] += (new_p ? rp[e] : 0.0) * t;
     }
-    block_sum<6>(acc, L.red, L.scal);
+    block_sum<4>(acc, L.red, L.scal);
     resid = sqrt(L.scal[0]);
     const double tt0 = L.scal[1];
     const double dxw = L.scal[2];
     const double dpw = new_p ? L.scal[3] : 0.0;
+    const bool was_fresh = fresh;
     have_p = new_p || (have_p && fresh);
     if (fresh) have_p = false;
     fresh = false;
+    // x, Ax (and p, Ap) back to memory
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int i = tid + e * kBatchThreads;
+      if (i < nsi) {
+        xv[i] = rx[e];
+        ax[i] = rax[e];
+        if (new_p) {
+          pv[i] = rp[e];
+          ap[i] = rap[e];
+        }
+      }
+    }
+    (void)was_fresh;
     IFCI_MARK(kPhPassA);
 
     const double tol = (phase == 32) ? A.r_tol_inner : A.r_tol;
@@ -1104,7 +1174,11 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
       if (phase == 32) {
         // FP64 refinement: sigma of x in FP64, then continue in FP64
         phase = 64;
-        for (int64_t i = tid; i < ns; i += blockDim.x) L.tv[i] = xv[i];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+          const int i = tid + e * kBatchThreads;
+          if (i < nsi) L.tv[i] = rx[e];
+        }
         fresh = true;
         __syncthreads();
         if (iters >= A.max_iter) break;
@@ -1114,38 +1188,43 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
       break;
     }
     if (iters >= A.max_iter) break;
-    // ---- orthogonalise w against x and p, normalise, store
+    // ---- orthogonalise t against x and p (twice if it cancels), normalise:
+    // the next w
     double acc2[3] = {0.0, 0.0, 0.0};
-    for (int64_t i = tid; i < ns; i += blockDim.x) {
-      double t = L.tv[i] - dxw * xv[i];
-      if (have_p) t -= dpw * pv[i];
-      L.tv[i] = t;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      double t = rt[e] - dxw * rx[e];
+      if (have_p) t -= dpw * rp[e];
+      rt[e] = t;
       acc2[0] += t * t;
-      acc2[1] += xv[i] * t;
-      if (have_p) acc2[2] += pv[i] * t;
+      acc2[1] += rx[e] * t;
+      acc2[2] += (have_p ? rp[e] : 0.0) * t;
     }
     block_sum<3>(acc2, L.red, L.scal);
     double tt = L.scal[0];
     if (tt < 0.5 * tt0) {
-      const double c0 = L.scal[1], c1 = L.scal[2];
-      __syncthreads();
+      const double c0 = L.scal[1], c1 = have_p ? L.scal[2] : 0.0;
       double acc3[1] = {0.0};
-      for (int64_t i = tid; i < ns; i += blockDim.x) {
-        double t = L.tv[i] - c0 * xv[i];
-        if (have_p) t -= c1 * pv[i];
-        L.tv[i] = t;
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        double t = rt[e] - c0 * rx[e];
+        if (have_p) t -= c1 * rp[e];
+        rt[e] = t;
         acc3[0] += t * t;
       }
       block_sum<1>(acc3, L.red, L.scal);
       tt = L.scal[0];
     }
-    __syncthreads();
     if (!(tt > 1e-28)) break;  // no new direction: stagnated
     const double inv = 1.0 / sqrt(tt);
-    for (int64_t i = tid; i < ns; i += blockDim.x) {
-      const double t = L.tv[i] * inv;
-      L.tv[i] = t;
-      wv[i] = t;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int i = tid + e * kBatchThreads;
+      if (i < nsi) {
+        const double t = rt[e] * inv;
+        L.tv[i] = t;
+        wv[i] = t;
+      }
     }
     __syncthreads();
     IFCI_MARK(kPhOrtho);

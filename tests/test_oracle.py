@@ -372,3 +372,16 @@ def test_sigma_rows_equal_dense_product():
     e, v, gap = fci.lowest_symmetric(H, n_str)
     r = H @ v - e * v
     assert certify.residual_bound(np.linalg.norm(r), gap) < 1e-12
+
+
+def test_sigma_rows_strings_equal_dense_product():
+    """String-addressed rows (no determinant list) against the dense
+    Slater-Condon product of a single body with no core."""
+    p = synthetic.single(6, 12, 11)
+    dets, n_str, act = fci.increment_dets(p.n_orb, p.bodies, p.nocc, (0,))
+    H = hamiltonian.build(dets, p.h, p.eri, act)
+    c = synthetic.random_vector(len(dets), 6)
+    rows = list(range(0, len(dets), 13))
+    got = certify.sigma_rows_strings(rows, 3, c, p.h, p.eri)
+    assert np.abs(got - (H @ c)[rows]).max() < 1e-12
+    assert np.abs(got - certify.sigma_rows(rows, dets, c, p.h, p.eri, act)).max() < 1e-12
