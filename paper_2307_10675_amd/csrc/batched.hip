@@ -874,62 +874,80 @@ __device__ __forceinline__ void solve_one(const SolveArgs& A, int pos, char* lds
   }
 }
 
-// Lowest eigenpair of the symmetric 3 x 3 matrix g by cyclic Jacobi
-// rotations in registers (every loop has fixed bounds, so nothing is
-// indexed dynamically).  A 2 x 2 problem is passed with g[2][2] far above
-// the spectrum and a zero last row.  Returns theta and z (unit).
-__device__ inline void small_eig3(double g[3][3], double* theta, double z[3]) {
-  double v[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
-#pragma unroll 1
-  for (int sweep = 0; sweep < 16; ++sweep) {
-    // per-pair test: a decoupled sentinel row must not mask the others.
-    // Rotations below 1e-15 of the pair's diagonal are skipped: they would
-    // move the eigenvalue by ~1e-30 relative, while FP64 rounding keeps
-    // regenerating off-diagonal noise near 1e-16 that must not be chased.
-    bool rotated = false;
-#pragma unroll
-    for (int pq = 0; pq < 3; ++pq) {
-      const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
-      const double apq = g[p][q];
-      if (fabs(apq) > 1e-15 * (fabs(g[p][p]) + fabs(g[q][q])) && fabs(apq) > 1e-300) {
-        rotated = true;
-        const double tau = (g[q][q] - g[p][p]) / (2.0 * apq);
-        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-        const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const double gip = g[i][p], giq = g[i][q];
-          g[i][p] = c * gip - sn * giq;
-          g[i][q] = sn * gip + c * giq;
-        }
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const double gpi = g[p][i], gqi = g[q][i];
-          g[p][i] = c * gpi - sn * gqi;
-          g[q][i] = sn * gpi + c * gqi;
-        }
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const double vp = v[i][p], vq = v[i][q];
-          v[i][p] = c * vp - sn * vq;
-          v[i][q] = sn * vp + c * vq;
-        }
-      }
+// Lowest eigenpair of a symmetric 3 x 3 matrix g (g[2][2] = 1e30 with a
+// zero third row and column marks a 2 x 2 problem).  2 x 2: closed form.
+// 3 x 3: Newton on the characteristic polynomial from below the Gershgorin
+// bound (monotone convergence to the lowest root), then the eigenvector as
+// the largest cross product of two rows of g - theta I.  Every thread of the
+// workgroup computes the same values.
+__device__ inline void small_eig3(const double g[3][3], double* theta, double z[3]) {
+  const double a = g[0][0], b = g[0][1], c = g[1][1];
+  if (g[2][2] >= 1e29) {
+    const double m = 0.5 * (a + c), h = 0.5 * (a - c);
+    const double l = m - sqrt(h * h + b * b);
+    double v0, v1;
+    if (fabs(a - l) >= fabs(c - l)) {
+      v0 = b;
+      v1 = l - a;
+    } else {
+      v0 = l - c;
+      v1 = b;
     }
-    if (!rotated) break;
+    if (v0 == 0.0 && v1 == 0.0) v0 = 1.0;
+    const double nr = 1.0 / sqrt(v0 * v0 + v1 * v1);
+    *theta = l;
+    z[0] = v0 * nr;
+    z[1] = v1 * nr;
+    z[2] = 0.0;
+    return;
   }
-  // lowest diagonal entry and its column
-  const int im = (g[1][1] < g[0][0]) ? ((g[2][2] < g[1][1]) ? 2 : 1) : ((g[2][2] < g[0][0]) ? 2 : 0);
-  *theta = im == 0 ? g[0][0] : (im == 1 ? g[1][1] : g[2][2]);
-  double nz = 0.0;
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    z[i] = im == 0 ? v[i][0] : (im == 1 ? v[i][1] : v[i][2]);
-    nz += z[i] * z[i];
+  const double d = g[0][2], e = g[1][2], f = g[2][2];
+  // det(l I - g) = l^3 + c2 l^2 + c1 l + c0
+  const double c2 = -(a + c + f);
+  const double c1 = a * c + a * f + c * f - b * b - d * d - e * e;
+  const double c0 = -(a * (c * f - e * e) - b * (b * f - e * d) + d * (b * e - c * d));
+  double l = fmin(a - fabs(b) - fabs(d), fmin(c - fabs(b) - fabs(e), f - fabs(d) - fabs(e)));
+  const double scale = 1.0 + fabs(a) + fabs(c) + fabs(f);
+#pragma unroll 1
+  for (int it = 0; it < 64; ++it) {
+    const double pv = ((l + c2) * l + c1) * l + c0;
+    const double dv = (3.0 * l + 2.0 * c2) * l + c1;
+    if (!(dv > 0.0)) break;
+    const double step = pv / dv;
+    l -= step;
+    if (fabs(step) <= 1e-15 * scale) break;
   }
-  nz = 1.0 / sqrt(nz);
-#pragma unroll
-  for (int i = 0; i < 3; ++i) z[i] *= nz;
+  const double r0[3] = {a - l, b, d}, r1[3] = {b, c - l, e}, r2[3] = {d, e, f - l};
+  auto cross = [](const double* u, const double* v, double* w) {
+    w[0] = u[1] * v[2] - u[2] * v[1];
+    w[1] = u[2] * v[0] - u[0] * v[2];
+    w[2] = u[0] * v[1] - u[1] * v[0];
+  };
+  double w01[3], w02[3], w12[3];
+  cross(r0, r1, w01);
+  cross(r0, r2, w02);
+  cross(r1, r2, w12);
+  const double n01 = w01[0] * w01[0] + w01[1] * w01[1] + w01[2] * w01[2];
+  const double n02 = w02[0] * w02[0] + w02[1] * w02[1] + w02[2] * w02[2];
+  const double n12 = w12[0] * w12[0] + w12[1] * w12[1] + w12[2] * w12[2];
+  const double* w = w01;
+  double nn = n01;
+  if (n02 > nn) {
+    w = w02;
+    nn = n02;
+  }
+  if (n12 > nn) {
+    w = w12;
+    nn = n12;
+  }
+  const double nr = 1.0 / sqrt(nn);
+  z[0] = w[0] * nr;
+  z[1] = w[1] * nr;
+  z[2] = w[2] * nr;
+  // Rayleigh quotient of the unit vector: the eigenvalue to rounding
+  double gz[3];
+  for (int i = 0; i < 3; ++i) gz[i] = g[i][0] * z[0] + g[i][1] * z[1] + g[i][2] * z[2];
+  *theta = z[0] * gz[0] + z[1] * gz[1] + z[2] * gz[2];
 }
 
 // Locally optimal block-free iteration (Davidson restarted every step to the
@@ -994,6 +1012,7 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
   double theta = 0.0, resid = 1e300;
   const int64_t o = (int64_t)id - A.first;
   const bool evict = A.evict && A.evict[o] != 0;
+  int bsp = 0;           // buffer parity of block_sum_1b
   bool fresh = true;     // x has no sigma yet (start or precision switch)
   bool have_p = false;
   double xap = 0.0, pap = 0.0;  // x.Ap and p.Ap of the current basis
@@ -1045,8 +1064,8 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
         rax[e] = rs[e];
         acc[0] += rx[e] * rs[e];
       }
-      block_sum<1>(acc, L.red, L.scal);
-      theta = L.scal[0];
+      block_sum_1b<1>(acc, L.red, bsp);
+      theta = acc[0];
       have_p = false;
     } else {
       // the new column of the 3 x 3 Rayleigh-Ritz matrix
@@ -1057,10 +1076,10 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
         acc[1] += rw[e] * rs[e];
         acc[2] += rp[e] * rs[e];
       }
-      block_sum<3>(acc, L.red, L.scal);
-      gxw = L.scal[0];
-      gww = L.scal[1];
-      gpw = have_p ? L.scal[2] : 0.0;
+      block_sum_1b<3>(acc, L.red, bsp);
+      gxw = acc[0];
+      gww = acc[1];
+      gpw = have_p ? acc[2] : 0.0;
     }
     IFCI_MARK(kPhSubspace);
     // ---- Rayleigh-Ritz on span{x, w, p}
@@ -1140,11 +1159,11 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
       acc[2] += x * t;
       acc[3] += (new_p ? rp[e] : 0.0) * t;
     }
-    block_sum<4>(acc, L.red, L.scal);
-    resid = sqrt(L.scal[0]);
-    const double tt0 = L.scal[1];
-    const double dxw = L.scal[2];
-    const double dpw = new_p ? L.scal[3] : 0.0;
+    block_sum_1b<4>(acc, L.red, bsp);
+    resid = sqrt(acc[0]);
+    const double tt0 = acc[1];
+    const double dxw = acc[2];
+    const double dpw = new_p ? acc[3] : 0.0;
     const bool was_fresh = fresh;
     have_p = new_p || (have_p && fresh);
     if (fresh) have_p = false;
@@ -1200,10 +1219,10 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
       acc2[1] += rx[e] * t;
       acc2[2] += (have_p ? rp[e] : 0.0) * t;
     }
-    block_sum<3>(acc2, L.red, L.scal);
-    double tt = L.scal[0];
+    block_sum_1b<3>(acc2, L.red, bsp);
+    double tt = acc2[0];
     if (tt < 0.5 * tt0) {
-      const double c0 = L.scal[1], c1 = have_p ? L.scal[2] : 0.0;
+      const double c0 = acc2[1], c1 = have_p ? acc2[2] : 0.0;
       double acc3[1] = {0.0};
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
@@ -1212,8 +1231,8 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
         rt[e] = t;
         acc3[0] += t * t;
       }
-      block_sum<1>(acc3, L.red, L.scal);
-      tt = L.scal[0];
+      block_sum_1b<1>(acc3, L.red, bsp);
+      tt = acc3[0];
     }
     if (!(tt > 1e-28)) break;  // no new direction: stagnated
     const double inv = 1.0 / sqrt(tt);

@@ -84,6 +84,31 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red, double* 
   __syncthreads();
 }
 
+// Same sums with one barrier: every thread adds the per-wave partials itself
+// (in the same fixed order) and gets the totals back in v[].  `red` holds two
+// buffers of 128 doubles (8 waves x NV <= 16) used alternately (`parity`
+// flips each call), so a call never overwrites partials that a slower
+// thread may still be reading from the call before.
+template <int NV>
+__device__ __forceinline__ void block_sum_1b(double (&v)[NV], double* red, int& parity) {
+  static_assert(NV <= 16, "two buffers of 8 waves x 16 values");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double* buf = red + parity * 128;
+  parity ^= 1;
+#pragma unroll
+  for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
+  if (lane == 0)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) buf[wave * NV + j] = v[j];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += buf[w * NV + j];
+    v[j] = s;
+  }
+}
+
 // Packed upper-triangle index: entry (a, b), a <= b, lives at b (b + 1) / 2 + a.
 __device__ __forceinline__ int64_t packed(int64_t a, int64_t b) {
   return a <= b ? tri(b) + a : tri(a) + b;
