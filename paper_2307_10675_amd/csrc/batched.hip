@@ -188,6 +188,13 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
   constexpr int MT = (NP + 15) / 16;
   constexpr int KS = (NP + 3) / 4;
   typedef Mfma<T> M;
+  // bit P set for the diagonal pairs P = i (i + 3) / 2 (the pair (i, i))
+  constexpr uint64_t kDiagPairs = [] {
+    uint64_t m = 0;
+    for (int i = 0; i < K; ++i) m |= 1ull << (i * (i + 3) / 2);
+    return m;
+  }();
+  static_assert(NP <= 64, "pair mask holds 64 pairs");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n = d.n_str, nlink = d.n_link;
   const T* cp = (const T*)L.cp;
@@ -206,13 +213,7 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
         double v = 0.0;
         if (P < NP && Q < NP) {
           v = V[P * NP + Q];
-          bool pd = false, qd = false;
-#pragma unroll
-          for (int i = 0; i < K; ++i) {
-            pd |= (P == i * (i + 3) / 2);
-            qd |= (Q == i * (i + 3) / 2);
-          }
-          if (pd && qd) v -= sh;
+          if ((kDiagPairs >> P) & (kDiagPairs >> Q) & 1) v -= sh;
         }
         afr[m][s] = (T)v;
       }
@@ -483,10 +484,31 @@ __device__ inline void prepare_sigma(const IncDev& d, const Lds& L) {
   __syncthreads();
 }
 
+// Entry i = (a, b) of the packed scaled vector, value v, into cp in the
+// layout of T, and the sigma accumulator slot cleared: the per-entry part of
+// prepare_sigma, for callers that produce the vector entry by entry.
+template <typename T>
+__device__ __forceinline__ void stage_entry(const IncDev& d, const Lds& L, int i, double v) {
+  int a, b;
+  unpack32(i, &a, &b);
+  T* cp = (T*)L.cp;
+  const T c = (T)(a == b ? v : v * kRSqrt2);
+  if (sizeof(T) == 4) {
+    const int ld = d.n_str + 1;
+    cp[a * ld + b] = c;
+    cp[b * ld + a] = c;
+  } else {
+    cp[i] = c;
+  }
+  L.sp[i] = 0.0;
+}
+
+// staged: the caller already wrote cp and cleared sp (stage_entry) and
+// synchronised; otherwise they are built here from L.tv.
 template <typename T, int K>
 __device__ inline void sigma_phase(const IncDev& d, const Lds& L, const double* V, double shift,
-                                   int et_waves) {
-  prepare_sigma<T>(d, L);
+                                   int et_waves, bool staged = false) {
+  if (!staged) prepare_sigma<T>(d, L);
   sigma_sector<T, K>(d, L, V, shift, et_waves);
   __syncthreads();
 }
@@ -1013,6 +1035,7 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
   const int64_t o = (int64_t)id - A.first;
   const bool evict = A.evict && A.evict[o] != 0;
   int bsp = 0;           // buffer parity of block_sum_1b
+  bool staged = false;   // cp / sp already hold the next sigma's input
   bool fresh = true;     // x has no sigma yet (start or precision switch)
   bool have_p = false;
   double xap = 0.0, pap = 0.0;  // x.Ap and p.Ap of the current basis
@@ -1020,9 +1043,10 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
   while (true) {
     // ---- sigma of the vector in L.tv (x when fresh, else w)
     if (phase == 32)
-      sigma_phase<float, K>(d, L, Vm, E0, ew32);
+      sigma_phase<float, K>(d, L, Vm, E0, ew32, staged);
     else
-      sigma_phase<double, K>(d, L, Vm, E0, ew64);
+      sigma_phase<double, K>(d, L, Vm, E0, ew64, staged);
+    staged = false;
     ++iters;
     IFCI_MARK(kPhSigma);
     // ---- this thread's NE entries of x, w, p, Ax, Ap and the diagonal, in
@@ -1236,15 +1260,20 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
     }
     if (!(tt > 1e-28)) break;  // no new direction: stagnated
     const double inv = 1.0 / sqrt(tt);
+    // w to memory and, in the layout of the next sigma, straight into cp
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
       const int i = tid + e * kBatchThreads;
       if (i < nsi) {
         const double t = rt[e] * inv;
-        L.tv[i] = t;
         wv[i] = t;
+        if (phase == 32)
+          stage_entry<float>(d, L, i, t);
+        else
+          stage_entry<double>(d, L, i, t);
       }
     }
+    staged = true;
     __syncthreads();
     IFCI_MARK(kPhOrtho);
   }

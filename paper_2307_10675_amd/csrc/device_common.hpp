@@ -113,6 +113,15 @@ __device__ __forceinline__ void block_sum_1b(double (&v)[NV], double* red, int& 
 __device__ __forceinline__ int64_t packed(int64_t a, int64_t b) {
   return a <= b ? tri(b) + a : tri(a) + b;
 }
+// 32-bit variant for indices below 2^24 (single-precision square root, then
+// an exact integer correction).
+__device__ __forceinline__ void unpack32(int i, int* a, int* b) {
+  int c = (int)((__builtin_sqrtf(8.0f * (float)i + 1.0f) - 1.0f) * 0.5f);
+  if (((c + 1) * (c + 2)) / 2 <= i) ++c;
+  if ((c * (c + 1)) / 2 > i) --c;
+  *b = c;
+  *a = i - (c * (c + 1)) / 2;
+}
 __device__ __forceinline__ void unpack(int64_t i, int* a, int* b) {
   int64_t c = (int64_t)((sqrt(8.0 * (double)i + 1.0) - 1.0) * 0.5);
   while (tri(c + 1) <= i) ++c;
