@@ -81,3 +81,39 @@ def test_full_order_six_bodies():
     rows = _rows(len(c), 7)
     r = certify.sigma_rows_strings(rows, 6, c, p.h, p.eri) - float(E[-1]) * c[rows]
     assert np.abs(r).max() <= 2e-9
+
+
+def test_rdm_ten_orbital_increment():
+    """Density matrices of a 10o10e increment (device-wide path): traces,
+    the Euler identity E = sum h gamma + sum (pq|rs) Gamma / 2, the pair
+    symmetries of Gamma, and central finite differences of the GPU energy
+    for two h entries."""
+    import torch
+    print("[large] rdm 10o10e", flush=True)
+    p = synthetic.single(10, 20, 4110)
+    plan, res = ifci.solve(p, r_tol=1e-10, max_iter=400)
+    dh, dg = plan.rdm()
+    torch.cuda.synchronize()
+    g1 = dh.cpu().numpy()
+    g2 = 2.0 * dg.cpu().numpy()
+    n_el = 10
+    assert abs(np.trace(g1) - n_el) < 1e-9
+    assert abs(np.einsum("pprr->", g2) - n_el * (n_el - 1)) < 1e-8
+    assert np.abs(g1 - g1.T).max() < 1e-10
+    assert np.abs(g2 - g2.transpose(2, 3, 0, 1)).max() < 1e-10
+    assert np.abs(g2 - g2.transpose(1, 0, 3, 2)).max() < 1e-10
+    E = float(res["E"][0])
+    assert abs((p.h * g1).sum() + 0.5 * (p.eri * g2).sum() - E) < 1e-9
+    w = np.linalg.eigvalsh(g1)
+    assert w.min() > -1e-10 and w.max() < 2 + 1e-10
+    step = 1e-5
+    for (a, b) in ((0, 0), (2, 7)):
+        hp, hm = p.h.copy(), p.h.copy()
+        for (x, y) in {(a, b), (b, a)}:
+            hp[x, y] += step
+            hm[x, y] -= step
+        ep = ifci.solve(synthetic.Problem(hp, p.eri, p.bodies, p.nocc, p.order), r_tol=1e-10, max_iter=400)[1]["total"]
+        em = ifci.solve(synthetic.Problem(hm, p.eri, p.bodies, p.nocc, p.order), r_tol=1e-10, max_iter=400)[1]["total"]
+        fd = (ep - em) / (2 * step)
+        an = sum(g1[x, y] for (x, y) in {(a, b), (b, a)})
+        assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (a, b, fd, an)
