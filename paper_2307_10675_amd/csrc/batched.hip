@@ -1195,13 +1195,13 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
     // x, Ax (and p, Ap) back to memory
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
-      const int i = tid + e * kBatchThreads;
+      const int i = tix + e * kBatchThreads;
       if (i < nsi) {
-        xv[i] = rx[e];
-        ax[i] = rax[e];
+        base[i] = rx[e];
+        base[mst + i] = rax[e];
         if (new_p) {
-          pv[i] = rp[e];
-          ap[i] = rap[e];
+          base[2 * sti + i] = rp[e];
+          base[mst + 2 * sti + i] = rap[e];
         }
       }
     }
@@ -1219,7 +1219,7 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
         phase = 64;
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
-          const int i = tid + e * kBatchThreads;
+          const int i = tix + e * kBatchThreads;
           if (i < nsi) L.tv[i] = rx[e];
         }
         fresh = true;
@@ -1263,10 +1263,10 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
     // w to memory and, in the layout of the next sigma, straight into cp
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
-      const int i = tid + e * kBatchThreads;
+      const int i = tix + e * kBatchThreads;
       if (i < nsi) {
         const double t = rt[e] * inv;
-        wv[i] = t;
+        base[sti + i] = t;
         if (phase == 32)
           stage_entry<float>(d, L, i, t);
         else
