@@ -337,67 +337,76 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
       const int a = min(16 * t + col, n);  // a = n: the zero tail
       return cp[pk32(a, j2[s])];
     };
-    // E[:, (a, b)] for one or two 16-string tiles (independent MFMA chains),
-    // stored transposed into the wave's slice.  Rows a >= n of the slice are
-    // padding.  The last MFMA row tile holds rows P >= npair (zero) that
-    // spill into the next string's row: it is stored first, so the other
-    // tiles overwrite what it spilled.
-    auto tiles = [&](auto tt, auto two) {
+    // E[:, (a, b)] for C consecutive 16-string tiles from tile t on (C
+    // independent MFMA chains per row tile), stored transposed into the
+    // wave's slice.  Rows a >= n of the slice are padding.  The last MFMA
+    // row tile holds rows P >= npair (zero) that spill into the next
+    // string's row: it is stored first, so the other tiles overwrite what it
+    // spilled.
+    auto tiles = [&](auto tt, auto cnt) {
       constexpr int t = decltype(tt)::value;
-      constexpr bool kTwo = decltype(two)::value;
-      typename M::acc acc0[MT], acc1[MT];
+      constexpr int C = decltype(cnt)::value;
+      typename M::acc acc[C][MT];
 #pragma unroll
-      for (int m = 0; m < MT; ++m) acc0[m] = acc1[m] = M::zero();
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[c][m] = M::zero();
       auto alpha = [&](int tt2, int s) -> T {
         const int i = tt2 * KS + s;
         return *(const T*)(L.root + ((ia[i >> 1] >> (16 * (i & 1))) & 0xFFFFu));
       };
       // loads of step s + 1 are issued ahead of the MFMAs of step s
-      T va0 = alpha(t, 0), vb0 = beta(t, 0), va1 = (T)0, vb1 = (T)0;
-      if (kTwo) {
-        va1 = alpha(t + 1, 0);
-        vb1 = beta(t + 1, 0);
+      T va[C], vb[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        va[c] = alpha(t + c, 0);
+        vb[c] = beta(t + c, 0);
       }
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        const T b0 = fma_t(sg[s], vb0, va0);
-        const T b1 = kTwo ? fma_t(sg[s], vb1, va1) : (T)0;
+        T bo[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) bo[c] = fma_t(sg[s], vb[c], va[c]);
         if (s + 1 < KS) {
-          va0 = alpha(t, s + 1);
-          vb0 = beta(t, s + 1);
-          if (kTwo) {
-            va1 = alpha(t + 1, s + 1);
-            vb1 = beta(t + 1, s + 1);
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            va[c] = alpha(t + c, s + 1);
+            vb[c] = beta(t + c, s + 1);
           }
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-          acc0[m] = M::mma(afr[m][s], b0, acc0[m]);
-          if (kTwo) acc1[m] = M::mma(afr[m][s], b1, acc1[m]);
-        }
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+          for (int c = 0; c < C; ++c) acc[c][m] = M::mma(afr[m][s], bo[c], acc[c][m]);
         __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int mm = 0; mm < MT; ++mm) {
         const int m = (mm + MT - 1) % MT;  // last row tile first
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          ebase[16 * t * NS + 16 * m + RSTEP * r] = acc0[m][r];
-          if (kTwo) ebase[16 * (t + 1) * NS + 16 * m + RSTEP * r] = acc1[m][r];
-        }
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < C; ++c) ebase[16 * (t + c) * NS + 16 * m + RSTEP * r] = acc[c][m][r];
         // the overlap is between lanes, which the compiler does not see:
         // keep the spilling stores ahead of the others
         if (mm == 0) asm volatile("" ::: "memory");
       }
     };
-    static_for<0, (NTM + 1) / 2>([&](auto hp) {
-      constexpr int t = 2 * decltype(hp)::value;
-      if (t + 1 < nt_count)
-        tiles(std::integral_constant<int, t>{}, std::true_type{});
-      else if (t < nt_count)
-        tiles(std::integral_constant<int, t>{}, std::false_type{});
-    });
+    // FP32 columns of full length run all their tiles in one pass (one
+    // accumulator drain per column, MT x NTM independent MFMAs per k-step);
+    // otherwise pairs of tiles
+    if (kFull && nt_count == NTM) {
+      tiles(std::integral_constant<int, 0>{}, std::integral_constant<int, NTM>{});
+    } else {
+      static_for<0, (NTM + 1) / 2>([&](auto hp) {
+        constexpr int t = 2 * decltype(hp)::value;
+        if (t + 1 < nt_count)
+          tiles(std::integral_constant<int, t>{}, std::integral_constant<int, 2>{});
+        else if (t < nt_count)
+          tiles(std::integral_constant<int, t>{}, std::integral_constant<int, 1>{});
+      });
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
