@@ -166,9 +166,14 @@ ifci_status ifci_set_integrals(ifci_plan_t plan, const double* h, const double* 
 ifci_status ifci_sigma(ifci_plan_t plan, int64_t inc, const double* c, double* sigma,
                        int32_t precision, ifci_stream_t stream);
 
-/* Same product restricted to symmetric c (C = C^T), as the batched Davidson
- * computes it: one workgroup, everything on chip.  Increments up to 12
- * active orbitals; IFCI_ERR_UNSUPPORTED otherwise. */
+/* Same product restricted to symmetric c (C = C^T, the sector the solvers
+ * search): c and sigma are packed scaled vectors (entry (a <= b) at
+ * b (b + 1) / 2 + a, off-diagonal entries times sqrt 2), n_str (n_str + 1) / 2
+ * FP64 each.  Increments that fit the batched solver (up to 8 active
+ * orbitals) run as that solver computes sigma, in one workgroup; half-filled
+ * increments of 10, 12 or 14 orbitals run the fused column kernel (one
+ * workgroup per beta string, E never leaves LDS; uses the workspace).
+ * Other shapes: IFCI_ERR_UNSUPPORTED.  c and sigma must not alias. */
 ifci_status ifci_sigma_sector(ifci_plan_t plan, int64_t inc, const double* c, double* sigma,
                               int32_t precision, ifci_stream_t stream);
 

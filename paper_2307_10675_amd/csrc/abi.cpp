@@ -356,13 +356,20 @@ ifci_status ifci_sigma_sector(ifci_plan_t p, int64_t inc, const double* c, doubl
     set_error("ifci_sigma_sector: bad increment, pointer or precision");
     return IFCI_ERR_ARG;
   }
-  if (!p->batched_ok[inc]) {
-    set_error("ifci_sigma_sector: increment too large for the on-chip path");
+  const IncDev& d = p->inc[inc];
+  if (!p->batched_ok[inc] && !sigma_column_supported(d)) {
+    set_error("ifci_sigma_sector: no symmetric-sector sigma for this increment shape");
     return IFCI_ERR_UNSUPPORTED;
   }
   ifci_status s = need_ints(p);
   if (s != IFCI_OK) return s;
   DeviceGuard g(p->device);
+  if (!p->batched_ok[inc]) {
+    HIP_TRY(launch_sigma_wide(d, p->d_inc, (int)inc, p->ws_ints(), p->d_tables, c, sigma, p->ws_E(), precision, 1,
+                              0.0, (hipStream_t)stream),
+            "ifci_sigma_sector");
+    return IFCI_OK;
+  }
   std::vector<int32_t> one(1, (int32_t)inc);
   HIP_TRY(launch_sigma_one(p->d_inc, (int)inc, p->ws_ints(), p->d_tables, c, sigma, precision, batch_lds(p, one),
                            (hipStream_t)stream),

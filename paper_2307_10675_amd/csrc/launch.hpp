@@ -20,9 +20,12 @@ hipError_t launch_sigma_one(const IncDev* incs, int inc, const double* ints, con
                             const double* c, double* sig, int precision, int lds_bytes,
                             hipStream_t st);
 
-// Device-wide sigma for any increment (E materialised in the workspace).
-// mode 0: c and sigma full [n_det] vectors, any c.  mode 1: c and sigma
-// packed scaled symmetric vectors.
+// Device-wide sigma for any increment.  mode 0: c and sigma full [n_det]
+// vectors, any c (E materialised in the workspace).  mode 1: c and sigma
+// packed scaled symmetric vectors; half-filled increments of 10, 12 or 14
+// orbitals take the fused column kernel (sigma_column_supported), others the
+// materialised E.
+bool sigma_column_supported(const IncDev& d);
 hipError_t launch_sigma_wide(const IncDev& d, const IncDev* d_inc_dev, int inc, const double* ints,
                              const int32_t* tables, const double* c, double* sig, double* E,
                              int precision, int mode, double shift, hipStream_t st);

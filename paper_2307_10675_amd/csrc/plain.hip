@@ -155,12 +155,290 @@ __global__ void __launch_bounds__(kWideThreads) gather_sym_kernel(IncDev d, cons
   sig[i] = kSqrt2 * ((double)s1 + (double)s2);
 }
 
+// ------------------------------------------------- fused column sigma (k 10..14)
+// Symmetric vectors of increments too large for the on-chip solver, one
+// workgroup per beta string b (a column of C).  With the pair table of
+// string J, (J1, s1) = E_Q J (read pair-major, 16 strings a row segment),
+// the column is
+//   D[Q][J] = s1 C[J1][b] + s2 C[J][J2]      ((J2, s2) = E_Q b),
+//   E[P][J] = sum_Q V[P][Q] D[Q][J]           (MFMA, 16-string tiles),
+//   S[E_P J][b] += s E[P][J]                  (scatter, LDS FP64 atomics),
+// the scatter form of the alpha gather (E_P is symmetric, so the pair table
+// is its own inverse).  sigma = S + S^T follows in a separate pass.  The
+// column copy of C, the A fragments of V and the FP64 accumulator S[:, b]
+// live in LDS; C (full, unscaled, in the contraction precision) and the
+// table rows come from L2.  Where LDS allows, the column copy is stored with
+// its negation and S with a negated twin, so one table index J + neg (n + 1)
+// addresses both the signed C value and the signed accumulator slot (S is
+// the first half minus the second).  FP64 sums of the FP32 products make S
+// practically independent of the atomic order.
+// FP32 runs three waves per SIMD (more waves hide the loads and VALU work
+// beside the MFMAs; four leave too few registers), FP64 two.
+template <typename T>
+constexpr int col_threads() { return sizeof(T) == 4 ? 768 : 512; }
+
+template <typename T, int K>
+struct ColShape {
+  static constexpr int NP = K * (K + 1) / 2;
+  static constexpr int MT = (NP + 15) / 16;
+  static constexpr int KS = (NP + 3) / 4;
+  static constexpr int KS2 = (KS + 1) / 2;  // FP32: two k-steps per LDS read
+  static constexpr int N = max_strings(K);
+  static constexpr int64_t vf_bytes = (int64_t)MT * (sizeof(T) == 4 ? 2 * KS2 : KS) * 64 * sizeof(T);
+  static constexpr int64_t brow_bytes = 32 * (int64_t)KS;  // [KS][4] uint32 row offsets + [KS][4] T signs
+  static constexpr bool kNeg =
+      vf_bytes + 2 * (int64_t)(N + 1) * sizeof(T) + 16 + 16 * (int64_t)(N + 1) + brow_bytes <= kMaxLds;
+  static constexpr int64_t col_bytes = (kNeg ? 2 : 1) * (int64_t)(N + 1) * sizeof(T);
+  static constexpr int64_t s_bytes = (kNeg ? 16 : 8) * (int64_t)(N + 1);
+  static constexpr int64_t lds = vf_bytes + ((col_bytes + 15) / 16) * 16 + s_bytes + brow_bytes;
+};
+
+// Packed scaled symmetric c -> full unscaled C [(n + 1) x n] of T (row n and
+// a tail of 16 entries zero).
+template <typename T>
+__global__ void __launch_bounds__(256) expand_sym_kernel(IncDev d, const double* __restrict__ c, T* __restrict__ cf) {
+  const int n = d.n_str;
+  const int64_t total = (int64_t)(n + 1) * n + 16;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / n;
+    const int cc = (int)(i - r * n);
+    double v = 0.0;
+    if (r < n) {
+      const int a = (int)r;
+      v = c[packed(a, cc)];
+      if (a != cc) v *= kRSqrt2;
+    }
+    cf[i] = (T)v;
+  }
+}
+
+// A fragments of V for the column kernel, in its LDS image, with the
+// diagonal-pair shift.  The rows of each 16-row tile are ordered so that
+// accumulator register r of lane L holds pair 16 m + 4 r + L / 16: the
+// pair-table entry of k-step 4 m + r that the lane loaded for D, which the
+// scatter reuses.  (FP64 MFMA rows already come in that order; FP32 rows come
+// as 4 (L / 16) + r, so fragment row rho takes pair 4 (rho % 4) + rho / 4.)
+// FP32 fragments are stored two k-steps per lane and entry (one 64-bit LDS
+// read per row tile and two k-steps).
+template <typename T, int K>
+__global__ void __launch_bounds__(256) col_frag_kernel(const double* __restrict__ V, double shift, double nel,
+                                                       T* __restrict__ vf) {
+  typedef ColShape<T, K> SH;
+  constexpr int NP = SH::NP, KS = SH::KS;
+  constexpr int KP = sizeof(T) == 4 ? 2 * SH::KS2 : KS;  // k-steps stored per row tile (FP32: padded to pairs)
+  const double sh = nel > 0.0 ? shift / (nel * nel) : 0.0;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= SH::MT * KP * 64) return;
+  const int L = i & 63, ms = i >> 6;
+  const int m = ms / KP, s = ms - m * KP;
+  const int rho = L & 15;
+  const int P = 16 * m + (sizeof(T) == 4 ? 4 * (rho & 3) + (rho >> 2) : rho), Q = 4 * s + (L >> 4);
+  double v = 0.0;
+  if (P < NP && Q < NP && s < KS) {
+    v = V[P * NP + Q];
+    // diagonal pairs are P = i (i + 3) / 2
+    auto diag = [](int x) {
+      const int r = (int)((__builtin_sqrt(8.0 * x + 9.0) - 3.0) * 0.5 + 0.5);
+      return r * (r + 3) / 2 == x;
+    };
+    if (diag(P) && diag(Q)) v -= sh;
+  }
+  if (sizeof(T) == 4)
+    vf[((m * SH::KS2 + (s >> 1)) * 64 + L) * 2 + (s & 1)] = (T)v;
+  else
+    vf[i] = (T)v;
+}
+
+template <typename T, int K>
+__global__ void __launch_bounds__(col_threads<T>()) sigma_column_kernel(IncDev d, const double* __restrict__ V,
+                                                                   const int32_t* __restrict__ ptab,
+                                                                   const int32_t* __restrict__ ptabT,
+                                                                   const T* __restrict__ cf,
+                                                                   const T* __restrict__ vfg,
+                                                                   double* __restrict__ Sm) {
+  typedef ColShape<T, K> SH;
+  typedef Mfma<T> M;
+  constexpr int NP = SH::NP, MT = SH::MT, KS = SH::KS, N = SH::N;
+  constexpr bool kNeg = SH::kNeg;
+  extern __shared__ __align__(16) char lds[];
+  T* Vf = (T*)lds;
+  T* ccol = (T*)(lds + SH::vf_bytes);
+  double* S = (double*)(lds + SH::vf_bytes + ((SH::col_bytes + 15) / 16) * 16);
+  uint32_t* browl = (uint32_t*)((char*)S + SH::s_bytes);
+  T* bsgl = (T*)(browl + 4 * KS);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int b = blockIdx.x;
+  // the A-fragment image of V (built once per sigma by col_frag_kernel)
+  for (int i = threadIdx.x; i < (int)(SH::vf_bytes / 16); i += blockDim.x)
+    ((float4*)Vf)[i] = ((const float4*)vfg)[i];
+  // column b of C (row b: C is symmetric), its negation, and S = 0
+  for (int j = threadIdx.x; j <= N; j += blockDim.x) {
+    const T v = j < N ? cf[(int64_t)b * N + j] : (T)0;
+    ccol[j] = v;
+    if (kNeg) ccol[N + 1 + j] = -v;
+  }
+  for (int j = threadIdx.x; j < (kNeg ? 2 : 1) * (N + 1); j += blockDim.x) S[j] = 0.0;
+  // beta part of k-step s for lanes with L / 16 = kq: browl[4 s + kq] the
+  // offset of row J2 of C (J2 = N, the zero row, for no link), bsgl the sign
+  for (int i = threadIdx.x; i < 4 * KS; i += blockDim.x) {
+    const int e = i < NP ? ptab[b * NP + i] : -1;
+    browl[i] = (uint32_t)((e < 0 ? N : (e >> 1)) * N);
+    bsgl[i] = (e >= 0 && (e & 1)) ? (T)-1 : (T)1;
+  }
+  __syncthreads();
+
+  const int kq = lane >> 4, col = lane & 15;
+  const int ntile = (N + 15) / 16;
+  for (int t = wave; t < ntile; t += nw) {
+    const int jr = 16 * t + col;
+    const bool jv = jr < N;
+    const int J = jv ? jr : N - 1;
+    // pair-table entries of this lane's k-steps (J1 << 1 | neg, J1 = N for
+    // no link) and the beta values, all issued first
+    // (beta loads run kBD k-steps ahead of their use)
+    constexpr int kBD = 8;
+    int32_t ent[KS];
+    T vb[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int Q = 4 * s + kq;
+      ent[s] = Q < NP ? ptabT[Q * N + J] : N;
+    }
+    auto beta = [&](int s) -> T { return cf[(int64_t)browl[4 * s + kq] + jr]; };
+#pragma unroll
+    for (int s = 0; s < kBD && s < KS; ++s) vb[s] = beta(s);
+    typename M::acc acc[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) acc[m] = M::zero();
+    auto alpha = [&](int s) -> T {
+      const int e = ent[s];
+      if (kNeg) return ccol[e];
+      const bool ng = e > N;
+      const T v = ccol[ng ? e - (N + 1) : e];
+      return ng ? -v : v;
+    };
+    T va = alpha(0);
+    float2 af[MT];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const T bop = fma_t(bsgl[4 * s + kq], vb[s], va);
+      if (s + 1 < KS) va = alpha(s + 1);
+      if (s + kBD < KS) vb[s + kBD] = beta(s + kBD);
+      if constexpr (sizeof(T) == 4) {
+        if ((s & 1) == 0) {
+#pragma unroll
+          for (int m = 0; m < MT; ++m) af[m] = ((const float2*)Vf)[(m * SH::KS2 + (s >> 1)) * 64 + lane];
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        T a;
+        if constexpr (sizeof(T) == 4)
+          a = (s & 1) == 0 ? af[m].x : af[m].y;
+        else
+          a = Vf[(m * KS + s) * 64 + lane];
+        acc[m] = M::mma(a, bop, acc[m]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // scatter: register r of row tile m holds pair 4 (4 m + r) + kq, whose
+    // table entry is ent[4 m + r]; S[E_P J] += s E[P][J]
+    if (jv) {
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int sp = 4 * m + r;
+          if (sp < KS && 4 * sp + kq < NP) {
+            const int e = ent[sp];
+            if (kNeg) {
+              if (e != N) lds_add(&S[e], (double)acc[m][r]);
+            } else if (e != N) {
+              const bool ng = e > N;
+              lds_add(&S[ng ? e - (N + 1) : e], ng ? -(double)acc[m][r] : (double)acc[m][r]);
+            }
+          }
+        }
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < N; j += blockDim.x) Sm[(int64_t)b * N + j] = kNeg ? S[j] - S[N + 1 + j] : S[j];
+}
+
+// sigma (packed scaled) = S + S^T from Sm[b][a] = S[a][b].
+__global__ void __launch_bounds__(256) sym_combine_kernel(IncDev d, const double* __restrict__ Sm,
+                                                          double* __restrict__ sig) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n_sym) return;
+  int a, b;
+  unpack(i, &a, &b);
+  const int64_t n = d.n_str;
+  sig[i] = a == b ? 2.0 * Sm[(int64_t)a * n + a] : kSqrt2 * (Sm[(int64_t)b * n + a] + Sm[(int64_t)a * n + b]);
+}
+
+bool sigma_column_supported(const IncDev& d) {
+  return d.na * 2 == d.k && (d.k == 10 || d.k == 12 || d.k == 14);
+}
+
+template <typename T, int K>
+static hipError_t launch_column_k(const IncDev& d, const double* V, const int32_t* ptab, const int32_t* ptabT,
+                                  const double* c, double* sig, double* ws, double shift, hipStream_t st) {
+  typedef ColShape<T, K> SH;
+  static_assert(SH::lds <= kMaxLds, "column sigma LDS");
+  const int n = d.n_str;
+  // workspace (256-byte aligned): full C, then S, then the fragment image,
+  // each starting on a 256-byte boundary
+  auto up = [](int64_t x) { return (x + 31) / 32 * 32; };
+  T* cf = (T*)ws;
+  const int64_t cf_elems = (int64_t)(n + 1) * n + 16;
+  const int64_t off_s = up((cf_elems * (int64_t)sizeof(T) + 7) / 8);
+  double* Sm = ws + off_s;
+  T* vfg = (T*)(ws + up(off_s + (int64_t)n * n));
+  const int nfrag = (int)(SH::vf_bytes / sizeof(T));
+  hipLaunchKernelGGL((col_frag_kernel<T, K>), dim3((nfrag + 255) / 256), dim3(256), 0, st, V, shift, 2.0 * d.na,
+                     vfg);
+  hipLaunchKernelGGL((expand_sym_kernel<T>), dim3(2048), dim3(256), 0, st, d, c, cf);
+  hipLaunchKernelGGL((sigma_column_kernel<T, K>), dim3(n), dim3(col_threads<T>()), (unsigned)SH::lds, st, d, V, ptab,
+                     ptabT, (const T*)cf, (const T*)vfg, Sm);
+  hipLaunchKernelGGL(sym_combine_kernel, dim3((unsigned)((d.n_sym + 255) / 256)), dim3(256), 0, st, d, Sm, sig);
+  return hipGetLastError();
+}
+
+static hipError_t launch_sigma_column(const IncDev& d, const double* V, const int32_t* ptab, const int32_t* ptabT,
+                                      const double* c, double* sig, double* ws, int precision, double shift,
+                                      hipStream_t st) {
+  static bool attr_done = false;
+  if (!attr_done) {
+    const void* fns[] = {(const void*)sigma_column_kernel<float, 10>, (const void*)sigma_column_kernel<double, 10>,
+                         (const void*)sigma_column_kernel<float, 12>, (const void*)sigma_column_kernel<double, 12>,
+                         (const void*)sigma_column_kernel<float, 14>, (const void*)sigma_column_kernel<double, 14>};
+    for (const void* f : fns) {
+      const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+      if (e != hipSuccess) return e;
+    }
+    attr_done = true;
+  }
+  const bool f32 = precision == IFCI_MIXED;
+  switch (d.k) {
+    case 10: return f32 ? launch_column_k<float, 10>(d, V, ptab, ptabT, c, sig, ws, shift, st)
+                        : launch_column_k<double, 10>(d, V, ptab, ptabT, c, sig, ws, shift, st);
+    case 12: return f32 ? launch_column_k<float, 12>(d, V, ptab, ptabT, c, sig, ws, shift, st)
+                        : launch_column_k<double, 12>(d, V, ptab, ptabT, c, sig, ws, shift, st);
+    case 14: return f32 ? launch_column_k<float, 14>(d, V, ptab, ptabT, c, sig, ws, shift, st)
+                        : launch_column_k<double, 14>(d, V, ptab, ptabT, c, sig, ws, shift, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_sigma_wide(const IncDev& d, const IncDev*, int, const double* ints, const int32_t* tables,
                              const double* c, double* sig, double* E, int precision, int mode, double shift,
                              hipStream_t st) {
   const double* V = ints + d.int_off + int_block(d.k).V;
   const int32_t* ptab = tables + d.pair_off;
   const int32_t* links = tables + d.link_off;
+  if (mode == 1 && sigma_column_supported(d))
+    return launch_sigma_column(d, V, ptab, tables + d.pairT_off, c, sig, E, precision, shift, st);
   const int64_t tiles = (d.n_det + 63) / 64;
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 g1((unsigned)tiles), blk(kWideThreads);

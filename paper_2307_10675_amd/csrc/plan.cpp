@@ -83,6 +83,17 @@ ShapeTables build_shape(int k, int na, std::vector<int32_t>& blob) {
       }
     }
   }
+  // the same pair table pair-major, [npair][n_str], as an index into a
+  // column copy stored with its negation: J + neg (n_str + 1), n_str for no
+  // link (a zero entry after the last string).  A row of strings for one
+  // pair is contiguous (coalesced loads over 16 consecutive strings).
+  t.pairT_off = (int64_t)blob.size();
+  blob.resize(blob.size() + (size_t)t.n_str * t.npair, 0);
+  for (int I = 0; I < t.n_str; ++I)
+    for (int Q = 0; Q < t.npair; ++Q) {
+      const int32_t e = blob[t.pair_off + (int64_t)I * t.npair + Q];
+      blob[t.pairT_off + (int64_t)Q * t.n_str + I] = e < 0 ? t.n_str : (e >> 1) + (e & 1) * (t.n_str + 1);
+    }
   return t;
 }
 
@@ -241,6 +252,7 @@ ifci_status plan_build(ifci_plan_s* P, const ifci_problem* pr, const ifci_option
       d.pair_off = t.pair_off;
       d.link_off = t.link_off;
       d.ord_off = t.ord_off;
+      d.pairT_off = t.pairT_off;
       d.int_off = P->ints_doubles;
       P->ints_doubles += int_block_size(k);
       d.vec_off = P->dav_doubles;

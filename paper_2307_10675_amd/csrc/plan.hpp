@@ -78,7 +78,7 @@ void set_error(const std::string& msg);
 // Tables of one (k, na) space, appended to `blob`.  Returns offsets.
 struct ShapeTables {
   int k, na, n_str, npair, n_link;
-  int64_t str_off, pair_off, link_off, ord_off;
+  int64_t str_off, pair_off, link_off, ord_off, pairT_off;
 };
 ShapeTables build_shape(int k, int na, std::vector<int32_t>& blob);
 int64_t binom(int n, int k);

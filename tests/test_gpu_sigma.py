@@ -96,7 +96,7 @@ def test_sigma_sector_equals_general_bitwise_symmetry(plan, refs):
 
 
 def test_sigma_sector_rejects_large(plan):
-    big = synthetic.single(10, 20, 4001)
+    big = synthetic.single(9, 18, 4001)  # 9 orbitals, 4 + 4 electrons: neither on-chip nor column shape
     p = ifci.Plan(big).attach(big.h, big.eri)
     import torch
     c = torch.zeros(p.increment(0).n_det, dtype=torch.float64, device="cuda")
