@@ -127,6 +127,34 @@ def cpu_baseline(problem, budget_s: float = 20.0):
                        f"extrapolated to all {len(incs)} increments (est. {total:.0f} s)")
 
 
+def large_sigma(torch, ifci, synthetic, n_orb=14, reps=5):
+    """Symmetric-sector sigma of one half-filled n_orb-orbital FCI space (the
+    single-FCI shape, seed 4000 + n_orb): the fused column kernel, FP32 and
+    FP64, timed with HIP events on the current stream."""
+    p = synthetic.single(n_orb, 2 * n_orb, 4000 + n_orb)
+    plan = ifci.Plan(p, solver=ifci.PLAIN).attach(p.h, p.eri)
+    n_str = int(round(plan.increment(0).n_det ** 0.5))
+    rng = np.random.default_rng(5)
+    c = torch.tensor(rng.standard_normal(n_str * (n_str + 1) // 2), device="cuda")
+    flops = f_sym(n_orb, n_orb // 2)
+    out = {"shape": f"{n_orb}o{n_orb}e, {n_str ** 2:,} determinants, sector {n_str * (n_str + 1) // 2:,}",
+           "flops_per_sigma": flops}
+    for name, prec, peak in (("fp32", ifci.MIXED, PEAK["fp32_mfma"]), ("fp64", ifci.FP64, PEAK["fp64_mfma"])):
+        plan.sigma_sector(0, c, precision=prec)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            plan.sigma_sector(0, c, precision=prec)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": ms, "tflops": flops / (ms * 1e-3) / 1e12, "frac_mfma_peak": flops / (ms * 1e-3) / peak}
+    del plan
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +162,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the 14o14e sigma measurement")
+    ap.add_argument("--only-large", action="store_true",
+                    help="measure only the 14o14e sigma (fused column kernel) and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a kernel of known "
                          "traffic, to scale HBM byte counters)")
@@ -146,7 +177,6 @@ def main():
 
     from paper_2307_10675_amd import ifci, synthetic
 
-    problem = synthetic.workload(2)
     dev = torch.device("cuda", 0)
     if a.copy_calibration > 0:
         src = torch.ones(a.copy_calibration << 18, dtype=torch.float32, device=dev)
@@ -155,6 +185,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if a.only_large:
+        print(json.dumps({"large_sigma": large_sigma(torch, ifci, synthetic)}), flush=True)
+        return
+    problem = synthetic.workload(2)
     h = torch.tensor(problem.h, dtype=torch.float64, device=dev)
     eri = torch.tensor(problem.eri, dtype=torch.float64, device=dev).contiguous()
 
@@ -226,6 +260,8 @@ def main():
             "kernel_ms_per_launch": mixed["kernel_ms"],
         },
     }
+    if not a.no_large:
+        out["detail"]["large_sigma"] = large_sigma(torch, ifci, synthetic)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(problem)
     print(json.dumps(out), flush=True)
