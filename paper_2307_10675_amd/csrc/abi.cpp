@@ -2,10 +2,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "launch.hpp"
@@ -71,6 +74,12 @@ void free_device(ifci_plan_s* P) {
   free_one(P->d_rdm_off);
   free_one(P->d_loc);
   free_one(P->d_w_inc);
+  for (hipStream_t s : P->slot_streams) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : P->slot_events) (void)hipEventDestroy(e);
+  if (P->fork_event) (void)hipEventDestroy(P->fork_event);
+  P->slot_streams.clear();
+  P->slot_events.clear();
+  P->fork_event = nullptr;
   P->on_device = false;
 }
 
@@ -440,7 +449,8 @@ ifci_status ifci_davidson(ifci_plan_t p, int64_t first, int64_t count, double* e
       HIP_TRY(hipMemcpyAsync(ev.data(), evict_mask, count, hipMemcpyDeviceToHost, st), "ifci_davidson");
       HIP_TRY(hipStreamSynchronize(st), "ifci_davidson");
     }
-    for (int32_t i : rest) {
+    // one device-wide solve: slot scratch, its stream
+    auto solve_one_plain = [&](int32_t i, int slot, hipStream_t sst) -> hipError_t {
       const IncDev& d = p->inc[i];
       PlainArgs A;
       A.d = d;
@@ -449,21 +459,67 @@ ifci_status ifci_davidson(ifci_plan_t p, int64_t first, int64_t count, double* e
       A.ints = p->ws_ints();
       A.tables = p->d_tables;
       A.dav = p->ws_dav() + d.vec_off;
-      A.E = p->ws_E();
-      A.tmp = p->ws_tmp();
-      A.part = p->ws_part();
-      A.state = p->ws_state();
+      A.E = p->ws_E(slot);
+      A.tmp = p->ws_tmp(slot);
+      A.part = p->ws_part(slot);
+      A.state = p->ws_state(slot);
       A.precision = p->opt.precision;
       A.max_iter = p->opt.max_iter;
-      A.max_space = p->opt.max_space;
+      A.max_space = d.mspace;  // the block's subspace (12 where 3 selects the on-chip iteration)
       A.r_tol = p->opt.r_tol;
       A.r_tol_inner = p->opt.r_tol_inner;
       A.e_const = p->e_const;
       A.evict = evict_mask ? ev[i - first] != 0 : false;
       const int64_t o = i - first;
-      HIP_TRY(run_plain(A, e_out + o, status_out + o, iters_out ? iters_out + o : nullptr,
-                        resid_out ? resid_out + o : nullptr, st),
-              "ifci_davidson plain");
+      return run_plain(A, e_out + o, status_out + o, iters_out ? iters_out + o : nullptr,
+                       resid_out ? resid_out + o : nullptr, sst);
+    };
+    const int W = (int)std::min<size_t>((size_t)p->n_slots, rest.size());
+    if (W <= 1) {
+      for (int32_t i : rest) HIP_TRY(solve_one_plain(i, 0, st), "ifci_davidson plain");
+    } else {
+      // Several increments at once, each driven by a host thread on its own
+      // stream with its own scratch slot (a device-wide solve waits on the
+      // host every iteration; other solves fill the GPU meanwhile).  The
+      // worker streams start after the work already queued on `st`, and
+      // `st` continues after all of them.
+      if ((int)p->slot_streams.size() < W) {
+        if (!p->fork_event) HIP_TRY(hipEventCreateWithFlags(&p->fork_event, hipEventDisableTiming), "ifci_davidson");
+        while ((int)p->slot_streams.size() < W) {
+          hipStream_t ss;
+          hipEvent_t se;
+          HIP_TRY(hipStreamCreateWithFlags(&ss, hipStreamNonBlocking), "ifci_davidson stream");
+          HIP_TRY(hipEventCreateWithFlags(&se, hipEventDisableTiming), "ifci_davidson event");
+          p->slot_streams.push_back(ss);
+          p->slot_events.push_back(se);
+        }
+      }
+      prepare_sigma_wide();
+      HIP_TRY(hipEventRecord(p->fork_event, st), "ifci_davidson");
+      for (int w = 0; w < W; ++w) HIP_TRY(hipStreamWaitEvent(p->slot_streams[w], p->fork_event, 0), "ifci_davidson");
+      std::atomic<size_t> next(0);
+      std::mutex err_mu;
+      hipError_t first_err = hipSuccess;
+      std::vector<std::thread> pool;
+      pool.reserve(W);
+      for (int w = 0; w < W; ++w)
+        pool.emplace_back([&, w] {
+          hipError_t e = hipSetDevice(p->device);
+          while (e == hipSuccess) {
+            const size_t j = next.fetch_add(1);
+            if (j >= rest.size()) break;
+            e = solve_one_plain(rest[j], w, p->slot_streams[w]);
+          }
+          if (e == hipSuccess) e = hipEventRecord(p->slot_events[w], p->slot_streams[w]);
+          if (e != hipSuccess) {
+            std::lock_guard<std::mutex> lk(err_mu);
+            if (first_err == hipSuccess) first_err = e;
+            next.store(rest.size());
+          }
+        });
+      for (std::thread& t : pool) t.join();
+      HIP_TRY(first_err, "ifci_davidson plain (concurrent)");
+      for (int w = 0; w < W; ++w) HIP_TRY(hipStreamWaitEvent(st, p->slot_events[w], 0), "ifci_davidson");
     }
   }
   for (int64_t i = first; i < first + count; ++i) p->solved[i] = 1;
@@ -494,7 +550,7 @@ ifci_status ifci_vector(ifci_plan_t p, int64_t inc, double* c_out, ifci_stream_t
   }
   DeviceGuard g(p->device);
   const IncDev& d = p->inc[inc];
-  const double* X = p->ws_dav() + d.vec_off + 2 * (int64_t)p->opt.max_space * d.stride + d.stride;
+  const double* X = p->ws_dav() + d.vec_off + 2 * (int64_t)d.mspace * d.stride + d.stride;
   HIP_TRY(launch_expand(d, X, c_out, (hipStream_t)stream), "ifci_vector");
   return IFCI_OK;
 }

@@ -23,7 +23,7 @@ struct IncDev {
   int32_t n_link;  // na (k - na + 1)
   int32_t n_core;
   int32_t id;      // canonical increment index
-  int32_t pad;
+  int32_t mspace;  // subspace vectors of this increment's Davidson block
   int64_t n_det;   // n_str^2
   int64_t n_sym;   // n_str (n_str + 1) / 2
   int64_t stride;  // padded n_sym used for packed vectors

@@ -12,6 +12,8 @@
 //                      + sum over links of beta(I) of sign E[Q][(alpha, J)].
 // For symmetric c, E is symmetric in its two string indices and the beta
 // gather is the transpose of the alpha gather.
+#include <mutex>
+
 #include "device_common.hpp"
 #include "launch.hpp"
 
@@ -405,20 +407,27 @@ static hipError_t launch_column_k(const IncDev& d, const double* V, const int32_
   return hipGetLastError();
 }
 
-static hipError_t launch_sigma_column(const IncDev& d, const double* V, const int32_t* ptab, const int32_t* ptabT,
-                                      const double* c, double* sig, double* ws, int precision, double shift,
-                                      hipStream_t st) {
-  static bool attr_done = false;
-  if (!attr_done) {
+// One-time set-up of the column kernels (their LDS exceeds the default
+// limit); safe to call from several host threads.
+hipError_t prepare_sigma_wide() {
+  static std::once_flag once;
+  static hipError_t status = hipSuccess;
+  std::call_once(once, [] {
     const void* fns[] = {(const void*)sigma_column_kernel<float, 10>, (const void*)sigma_column_kernel<double, 10>,
                          (const void*)sigma_column_kernel<float, 12>, (const void*)sigma_column_kernel<double, 12>,
                          (const void*)sigma_column_kernel<float, 14>, (const void*)sigma_column_kernel<double, 14>};
     for (const void* f : fns) {
       const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
-      if (e != hipSuccess) return e;
+      if (e != hipSuccess && status == hipSuccess) status = e;
     }
-    attr_done = true;
-  }
+  });
+  return status;
+}
+
+static hipError_t launch_sigma_column(const IncDev& d, const double* V, const int32_t* ptab, const int32_t* ptabT,
+                                      const double* c, double* sig, double* ws, int precision, double shift,
+                                      hipStream_t st) {
+  if (prepare_sigma_wide() != hipSuccess) return hipErrorInvalidValue;
   const bool f32 = precision == IFCI_MIXED;
   switch (d.k) {
     case 10: return f32 ? launch_column_k<float, 10>(d, V, ptab, ptabT, c, sig, ws, shift, st)

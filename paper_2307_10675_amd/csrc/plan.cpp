@@ -3,6 +3,8 @@
 // active-space shape, expansion weights and the workspace layout.
 #include "plan.hpp"
 
+#include "launch.hpp"
+
 #include <algorithm>
 #include <cstring>
 #include <map>
@@ -255,8 +257,13 @@ ifci_status plan_build(ifci_plan_s* P, const ifci_problem* pr, const ifci_option
       d.pairT_off = t.pairT_off;
       d.int_off = P->ints_doubles;
       P->ints_doubles += int_block_size(k);
+      // increments for the device-wide solver get the default subspace
+      // when 3 selects the on-chip three-vector iteration
+      const bool on_chip = op->solver != IFCI_SOLVER_PLAIN && k <= 8 &&
+                           ifci::batched_lds_bytes(k, t.n_str, t.n_link) <= ifci::kMaxLds;
+      d.mspace = (!on_chip && mmax == 3) ? 12 : mmax;
       d.vec_off = P->dav_doubles;
-      P->dav_doubles += vec_block_size(d.stride, mmax);
+      P->dav_doubles += vec_block_size(d.stride, d.mspace);
       P->max_ndet = std::max(P->max_ndet, d.n_det);
       P->max_npair = std::max<int64_t>(P->max_npair, d.npair);
       P->max_stride = std::max(P->max_stride, d.stride);
@@ -286,17 +293,27 @@ ifci_status plan_build(ifci_plan_s* P, const ifci_problem* pr, const ifci_option
   off = align_up(off + P->ints_doubles * 8, A);
   P->off_dav = off;
   off = align_up(off + P->dav_doubles * 8, A);
-  P->E_doubles = P->max_npair * P->max_ndet;
+  P->E_doubles = align_up(P->max_npair * P->max_ndet, 32);
+  // device-wide solves run several increments at once when their scratch is
+  // small: up to 8 slots within 2 GiB of E scratch beyond the first, and no
+  // more slots than increments that can take that path
+  {
+    int64_t n_wide = 0;
+    for (const ifci::IncDev& d : P->inc)
+      if (op->solver == IFCI_SOLVER_PLAIN || d.k > 8) ++n_wide;
+    const int64_t by_mem = 1 + ((int64_t)2 << 30) / std::max<int64_t>(1, P->E_doubles * 8);
+    P->n_slots = (int)std::max<int64_t>(1, std::min<int64_t>({8, by_mem, n_wide}));
+  }
   P->off_E = off;
-  off = align_up(off + P->E_doubles * 8, A);
-  P->tmp_doubles = 4 * P->max_stride + 8;
+  off = align_up(off + P->n_slots * P->E_doubles * 8, A);
+  P->tmp_doubles = align_up(4 * P->max_stride + 8, 32);
   P->off_tmp = off;
-  off = align_up(off + P->tmp_doubles * 8, A);
+  off = align_up(off + P->n_slots * P->tmp_doubles * 8, A);
   P->part_doubles = 2048 * 40;
   P->off_part = off;
-  off = align_up(off + P->part_doubles * 8, A);
+  off = align_up(off + P->n_slots * P->part_doubles * 8, A);
   P->off_state = off;
-  off = align_up(off + 4096 * 8, A);
+  off = align_up(off + P->n_slots * 4096 * 8, A);
   P->off_rdm = off;
   off = align_up(off + P->rdm_doubles * 8, A);
   P->off_misc = off;

@@ -33,6 +33,12 @@ struct ifci_plan_s {
   int64_t off_ints = 0, off_dav = 0, off_E = 0, off_tmp = 0, off_part = 0, off_state = 0,
           off_rdm = 0, off_misc = 0, off_eps = 0, ws_bytes = 0;
   int64_t E_doubles = 0, tmp_doubles = 0, part_doubles = 0;
+  // concurrent device-wide solves: each slot has its own E, tmp, part and
+  // state scratch and (created on first use) its own stream and event
+  int n_slots = 1;
+  std::vector<hipStream_t> slot_streams;
+  std::vector<hipEvent_t> slot_events;
+  hipEvent_t fork_event = nullptr;
   // device
   ifci::IncDev* d_inc = nullptr;
   int32_t* d_orbs = nullptr;
@@ -62,10 +68,10 @@ struct ifci_plan_s {
 
   double* ws_ints() const { return (double*)(ws + off_ints); }
   double* ws_dav() const { return (double*)(ws + off_dav); }
-  double* ws_E() const { return (double*)(ws + off_E); }
-  double* ws_tmp() const { return (double*)(ws + off_tmp); }
-  double* ws_part() const { return (double*)(ws + off_part); }
-  double* ws_state() const { return (double*)(ws + off_state); }
+  double* ws_E(int slot = 0) const { return (double*)(ws + off_E) + (int64_t)slot * E_doubles; }
+  double* ws_tmp(int slot = 0) const { return (double*)(ws + off_tmp) + (int64_t)slot * tmp_doubles; }
+  double* ws_part(int slot = 0) const { return (double*)(ws + off_part) + (int64_t)slot * part_doubles; }
+  double* ws_state(int slot = 0) const { return (double*)(ws + off_state) + (int64_t)slot * 4096; }
   double* ws_rdm() const { return (double*)(ws + off_rdm); }
   double* ws_misc() const { return (double*)(ws + off_misc); }
   double* ws_eps() const { return (double*)(ws + off_eps); }

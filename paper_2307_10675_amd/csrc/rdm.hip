@@ -41,7 +41,8 @@ __global__ void __launch_bounds__(kRdmThreads) rdm_kernel(const IncDev* __restri
   const int nw = blockDim.x >> 6, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int t0 = blockIdx.y * nw * kTilesPerWave;
   if (t0 >= ntiles) return;
-  const double* X = dav + d.vec_off + 2 * (int64_t)mmax * d.stride + d.stride;
+  const double* X = dav + d.vec_off + 2 * (int64_t)d.mspace * d.stride + d.stride;
+  (void)mmax;
   const int32_t* ord = tables + d.ord_off;
   double* Dc = (double*)lds;                       // [k2p][kRdmChunk]
   const int k2p = nt * 16;
