@@ -162,7 +162,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-large", action="store_true", help="skip the 14o14e sigma measurement")
+    ap.add_argument("--no-large", action="store_true", help="skip the 14o14e and 16o16e sigma measurements")
     ap.add_argument("--only-large", action="store_true",
                     help="measure only the 14o14e sigma (fused column kernel) and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -186,7 +186,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if a.only_large:
-        print(json.dumps({"large_sigma": large_sigma(torch, ifci, synthetic)}), flush=True)
+        print(json.dumps({"large_sigma": large_sigma(torch, ifci, synthetic),
+                          "large_sigma_16o": large_sigma(torch, ifci, synthetic, n_orb=16, reps=3)}), flush=True)
         return
     problem = synthetic.workload(2)
     h = torch.tensor(problem.h, dtype=torch.float64, device=dev)
@@ -262,6 +263,7 @@ def main():
     }
     if not a.no_large:
         out["detail"]["large_sigma"] = large_sigma(torch, ifci, synthetic)
+        out["detail"]["large_sigma_16o"] = large_sigma(torch, ifci, synthetic, n_orb=16, reps=3)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(problem)
     print(json.dumps(out), flush=True)

@@ -349,8 +349,13 @@ ifci_status ifci_sigma(ifci_plan_t p, int64_t inc, const double* c, double* sigm
   }
   ifci_status s = need_ints(p);
   if (s != IFCI_OK) return s;
-  DeviceGuard g(p->device);
   const IncDev& d = p->inc[inc];
+  if (d.npair * d.n_det > p->E_doubles) {
+    set_error("ifci_sigma: the general product of this increment needs npair x n_det scratch "
+              "(use ifci_sigma_sector for symmetric vectors)");
+    return IFCI_ERR_UNSUPPORTED;
+  }
+  DeviceGuard g(p->device);
   HIP_TRY(launch_sigma_wide(d, p->d_inc, (int)inc, p->ws_ints(), p->d_tables, c, sigma, p->ws_E(), precision, 0,
                             0.0, (hipStream_t)stream),
           "ifci_sigma");

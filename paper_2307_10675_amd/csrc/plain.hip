@@ -368,6 +368,147 @@ __global__ void __launch_bounds__(col_threads<T>()) sigma_column_kernel(IncDev d
   for (int j = threadIdx.x; j < N; j += blockDim.x) Sm[(int64_t)b * N + j] = kNeg ? S[j] - S[N + 1 + j] : S[j];
 }
 
+// 16 orbitals (12,870 strings, 136 pairs) do not fit that LDS layout.  The
+// split variant keeps the same scheme with the column copy left in L2 (the
+// alpha values are read from C, kBD k-steps ahead like the beta values).
+// FP32 keeps all A fragments in LDS (one pass) with an FP32 accumulator (its
+// atomic order is not fixed: repeated products agree to FP32 rounding); FP64
+// keeps an FP64 accumulator and takes the fragments in passes of MTP row
+// tiles (each pass sweeps every tile of the column and rebuilds D; the MFMA
+// work is not repeated).
+template <typename T, int K>
+struct ColSplit {
+  static constexpr int NP = K * (K + 1) / 2;
+  static constexpr int MT = (NP + 15) / 16;
+  static constexpr int KS = (NP + 3) / 4;
+  static constexpr int KS2 = (KS + 1) / 2;
+  static constexpr int N = max_strings(K);
+  static constexpr bool kF32 = sizeof(T) == 4;
+  static constexpr int MTP = kF32 ? MT : 3;                // row tiles per pass
+  static constexpr int NPASS = (MT + MTP - 1) / MTP;
+  static constexpr int KSP = kF32 ? 2 * KS2 : KS;         // k-steps stored per row tile
+  typedef typename std::conditional<kF32, float, double>::type SA;  // accumulator
+  static constexpr int64_t vf_bytes = (int64_t)MTP * KSP * 64 * sizeof(T);
+  static constexpr int64_t col_bytes = 0;
+  static constexpr int64_t s_bytes = ((int64_t)N * sizeof(SA) + 15) / 16 * 16;
+  static constexpr int64_t brow_bytes = (int64_t)4 * KS * (4 + sizeof(T));
+  static constexpr int64_t lds = vf_bytes + col_bytes + s_bytes + brow_bytes;
+};
+
+constexpr int kSplitThreads = 512;  // two waves per SIMD: the single FP32 pass needs the registers
+
+template <typename T, int K>
+__global__ void __launch_bounds__(kSplitThreads) sigma_column_split_kernel(
+    IncDev d, const int32_t* __restrict__ ptab, const int32_t* __restrict__ ptabT, const T* __restrict__ cf,
+    const T* __restrict__ vfg, double* __restrict__ Sm) {
+  typedef ColSplit<T, K> SH;
+  typedef Mfma<T> M;
+  typedef typename SH::SA SA;
+  constexpr int NP = SH::NP, MT = SH::MT, KS = SH::KS, N = SH::N, MTP = SH::MTP;
+  constexpr bool kF32 = SH::kF32;
+  static_assert(SH::lds <= kMaxLds, "split column sigma LDS");
+  extern __shared__ __align__(16) char lds[];
+  T* Vf = (T*)lds;
+  SA* S = (SA*)(lds + SH::vf_bytes + SH::col_bytes);
+  uint32_t* browl = (uint32_t*)(lds + SH::vf_bytes + SH::col_bytes + SH::s_bytes);
+  T* bsgl = (T*)(browl + 4 * KS);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int b = blockIdx.x;
+  const T* crow = cf + (int64_t)b * N;  // column b of C (= row b)
+  for (int j = threadIdx.x; j < N; j += blockDim.x) S[j] = (SA)0;
+  for (int i = threadIdx.x; i < 4 * KS; i += blockDim.x) {
+    const int e = i < NP ? ptab[b * NP + i] : -1;
+    browl[i] = (uint32_t)((e < 0 ? N : (e >> 1)) * N);
+    bsgl[i] = (e >= 0 && (e & 1)) ? (T)-1 : (T)1;
+  }
+  const int kq = lane >> 4, col = lane & 15;
+  const int ntile = (N + 15) / 16;
+  static_for<0, SH::NPASS>([&](auto pp) {
+    constexpr int m0 = decltype(pp)::value * MTP;
+    constexpr int MP = (MT - m0) < MTP ? (MT - m0) : MTP;  // row tiles of this pass
+    __syncthreads();  // the previous pass is done with Vf
+    for (int i = threadIdx.x; i < (int)((int64_t)MP * SH::KSP * 64 * sizeof(T) / 16); i += blockDim.x)
+      ((float4*)Vf)[i] = ((const float4*)(vfg + (int64_t)m0 * SH::KSP * 64))[i];
+    __syncthreads();
+    for (int t = wave; t < ntile; t += nw) {
+      const int jr = 16 * t + col;
+      const bool jv = jr < N;
+      const int J = jv ? jr : N - 1;
+      constexpr int kBD = 8;  // loads run kBD k-steps ahead of their use
+      int32_t ent[KS];
+      T vb[KS], vaq[KS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int Q = 4 * s + kq;
+        ent[s] = Q < NP ? ptabT[Q * N + J] : N;
+      }
+      auto beta = [&](int s) -> T { return cf[(int64_t)browl[4 * s + kq] + jr]; };
+      // alpha value C[J1][b] signed, J1 + neg (N + 1) = ent (N: no link)
+      auto alpha = [&](int s) -> T {
+        const int e = ent[s];
+        const bool ng = e > N;
+        const int j1 = ng ? e - (N + 1) : e;
+        const T v = j1 < N ? crow[j1] : (T)0;
+        return ng ? -v : v;
+      };
+#pragma unroll
+      for (int s = 0; s < kBD && s < KS; ++s) {
+        vb[s] = beta(s);
+        vaq[s] = alpha(s);
+      }
+      typename M::acc acc[MP];
+#pragma unroll
+      for (int m = 0; m < MP; ++m) acc[m] = M::zero();
+      float2 af[MP];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const T bop = fma_t(bsgl[4 * s + kq], vb[s], vaq[s]);
+        if (s + kBD < KS) {
+          vb[s + kBD] = beta(s + kBD);
+          vaq[s + kBD] = alpha(s + kBD);
+        }
+        if constexpr (kF32) {
+          if ((s & 1) == 0) {
+#pragma unroll
+            for (int m = 0; m < MP; ++m) af[m] = ((const float2*)Vf)[(m * SH::KS2 + (s >> 1)) * 64 + lane];
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int m = 0; m < MP; ++m) {
+          T a;
+          if constexpr (kF32)
+            a = (s & 1) == 0 ? af[m].x : af[m].y;
+          else
+            a = Vf[(m * KS + s) * 64 + lane];
+          acc[m] = M::mma(a, bop, acc[m]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      // scatter: register r of row tile m0 + m holds pair 4 (4 (m0 + m) + r)
+      // + kq, whose table entry is ent[4 (m0 + m) + r]
+      if (jv) {
+#pragma unroll
+        for (int m = 0; m < MP; ++m)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int sp = 4 * (m0 + m) + r;
+            if (sp < KS && 4 * sp + kq < NP) {
+              const int e = ent[sp];
+              if (e != N) {
+                const bool ng = e > N;
+                const SA v = (SA)acc[m][r];
+                lds_add(&S[ng ? e - (N + 1) : e], ng ? -v : v);
+              }
+            }
+          }
+      }
+    }
+  });
+  __syncthreads();
+  for (int j = threadIdx.x; j < N; j += blockDim.x) Sm[(int64_t)b * N + j] = (double)S[j];
+}
+
 // sigma (packed scaled) = S + S^T from Sm[b][a] = S[a][b].
 __global__ void __launch_bounds__(256) sym_combine_kernel(IncDev d, const double* __restrict__ Sm,
                                                           double* __restrict__ sig) {
@@ -380,7 +521,16 @@ __global__ void __launch_bounds__(256) sym_combine_kernel(IncDev d, const double
 }
 
 bool sigma_column_supported(const IncDev& d) {
-  return d.na * 2 == d.k && (d.k == 10 || d.k == 12 || d.k == 14);
+  return d.na * 2 == d.k && (d.k == 10 || d.k == 12 || d.k == 14 || d.k == 16);
+}
+
+// Workspace doubles of the column path (full C of either precision, S, the
+// fragment image, with 256-byte alignment of each).
+int64_t sigma_column_ws_doubles(const IncDev& d) {
+  const int64_t n = d.n_str;
+  auto up = [](int64_t x) { return (x + 31) / 32 * 32; };
+  const int64_t np = (int64_t)d.k * (d.k + 1) / 2, mt = (np + 15) / 16, ks = (np + 3) / 4;
+  return up((n + 1) * n + 16) + up(n * n) + up(mt * (ks + 1) * 64) + 64;
 }
 
 template <typename T, int K>
@@ -407,6 +557,27 @@ static hipError_t launch_column_k(const IncDev& d, const double* V, const int32_
   return hipGetLastError();
 }
 
+template <typename T, int K>
+static hipError_t launch_column_split(const IncDev& d, const double* V, const int32_t* ptab, const int32_t* ptabT,
+                                      const double* c, double* sig, double* ws, double shift, hipStream_t st) {
+  typedef ColSplit<T, K> SH;
+  const int n = d.n_str;
+  auto up = [](int64_t x) { return (x + 31) / 32 * 32; };
+  T* cf = (T*)ws;
+  const int64_t cf_elems = (int64_t)(n + 1) * n + 16;
+  const int64_t off_s = up((cf_elems * (int64_t)sizeof(T) + 7) / 8);
+  double* Sm = ws + off_s;
+  T* vfg = (T*)(ws + up(off_s + (int64_t)n * n));
+  const int nfrag = (int)((int64_t)SH::MT * SH::KSP * 64);
+  hipLaunchKernelGGL((col_frag_kernel<T, K>), dim3((nfrag + 255) / 256), dim3(256), 0, st, V, shift, 2.0 * d.na,
+                     vfg);
+  hipLaunchKernelGGL((expand_sym_kernel<T>), dim3(4096), dim3(256), 0, st, d, c, cf);
+  hipLaunchKernelGGL((sigma_column_split_kernel<T, K>), dim3(n), dim3(kSplitThreads), (unsigned)SH::lds, st, d,
+                     ptab, ptabT, (const T*)cf, (const T*)vfg, Sm);
+  hipLaunchKernelGGL(sym_combine_kernel, dim3((unsigned)((d.n_sym + 255) / 256)), dim3(256), 0, st, d, Sm, sig);
+  return hipGetLastError();
+}
+
 // One-time set-up of the column kernels (their LDS exceeds the default
 // limit); safe to call from several host threads.
 hipError_t prepare_sigma_wide() {
@@ -415,7 +586,9 @@ hipError_t prepare_sigma_wide() {
   std::call_once(once, [] {
     const void* fns[] = {(const void*)sigma_column_kernel<float, 10>, (const void*)sigma_column_kernel<double, 10>,
                          (const void*)sigma_column_kernel<float, 12>, (const void*)sigma_column_kernel<double, 12>,
-                         (const void*)sigma_column_kernel<float, 14>, (const void*)sigma_column_kernel<double, 14>};
+                         (const void*)sigma_column_kernel<float, 14>, (const void*)sigma_column_kernel<double, 14>,
+                         (const void*)sigma_column_split_kernel<float, 16>,
+                         (const void*)sigma_column_split_kernel<double, 16>};
     for (const void* f : fns) {
       const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
       if (e != hipSuccess && status == hipSuccess) status = e;
@@ -436,6 +609,8 @@ static hipError_t launch_sigma_column(const IncDev& d, const double* V, const in
                         : launch_column_k<double, 12>(d, V, ptab, ptabT, c, sig, ws, shift, st);
     case 14: return f32 ? launch_column_k<float, 14>(d, V, ptab, ptabT, c, sig, ws, shift, st)
                         : launch_column_k<double, 14>(d, V, ptab, ptabT, c, sig, ws, shift, st);
+    case 16: return f32 ? launch_column_split<float, 16>(d, V, ptab, ptabT, c, sig, ws, shift, st)
+                        : launch_column_split<double, 16>(d, V, ptab, ptabT, c, sig, ws, shift, st);
     default: return hipErrorInvalidValue;
   }
 }

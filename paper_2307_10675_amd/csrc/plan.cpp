@@ -293,7 +293,19 @@ ifci_status plan_build(ifci_plan_s* P, const ifci_problem* pr, const ifci_option
   off = align_up(off + P->ints_doubles * 8, A);
   P->off_dav = off;
   off = align_up(off + P->dav_doubles * 8, A);
-  P->E_doubles = align_up(P->max_npair * P->max_ndet, 32);
+  // device-wide scratch: the materialised E (npair x n_det) where the
+  // general product may run; at 16 orbitals only the column path's (full C,
+  // S and fragments: 2.7 GB instead of 180 GB of E)
+  {
+    int64_t need = 0;
+    for (const ifci::IncDev& d : P->inc) {
+      int64_t e = d.npair * d.n_det;
+      if (ifci::sigma_column_supported(d))
+        e = d.k > 14 ? ifci::sigma_column_ws_doubles(d) : std::max(e, ifci::sigma_column_ws_doubles(d));
+      need = std::max(need, e);
+    }
+    P->E_doubles = align_up(need, 32);
+  }
   // device-wide solves run several increments at once when their scratch is
   // small: up to 8 slots within 2 GiB of E scratch beyond the first, and no
   // more slots than increments that can take that path

@@ -75,3 +75,35 @@ def test_column_sigma_repeatable():
         x = plan.sigma_sector(0, c, precision=prec).cpu().numpy()
         y = plan.sigma_sector(0, c, precision=prec).cpu().numpy()
         assert np.abs(x - y).max() <= 1e-13 * max(1.0, np.abs(x).max())
+
+
+def test_column_sigma_rows_16_orbitals():
+    """16o16e (165,636,900 determinants): the split column kernel (fragments
+    in passes; FP32 accumulates in FP32) on 24 sampled rows against the
+    oracle's Slater-Condon rows; the general product is unsupported at this
+    size and says so."""
+    import torch
+    print("[column] 16o16e rows", flush=True)
+    n, K, seed = 16, 32, 4216
+    p = synthetic.single(n, K, seed)
+    plan = ifci.Plan(p, solver=ifci.PLAIN).attach(p.h, p.eri)
+    n_str = int(round(np.sqrt(plan.increment(0).n_det)))
+    assert n_str == 12870
+    cp, C = _sym_vectors(n_str, seed + 1)
+    rng = np.random.default_rng(seed + 2)
+    rows = np.sort(rng.choice(n_str * n_str, 24, replace=False))
+    want = certify.sigma_rows_strings(rows, n // 2, C.reshape(-1), p.h, p.eri)
+    del C
+    ra, rb = rows // n_str, rows % n_str
+    lo, hi = np.minimum(ra, rb), np.maximum(ra, rb)
+    idx = hi * (hi + 1) // 2 + lo
+    ref = np.where(ra == rb, 1.0, np.sqrt(2.0)) * want
+    big = max(1.0, np.abs(want).max())
+    c = torch.tensor(cp, device="cuda")
+    for prec, tol in ((ifci.FP64, 1e-12 * n), (ifci.MIXED, 2e-5)):
+        got = plan.sigma_sector(0, c, precision=prec)[torch.tensor(idx, device="cuda")].cpu().numpy()
+        assert np.abs(got - ref).max() <= tol * big, (prec, np.abs(got - ref).max())
+    full = torch.zeros(n_str * n_str, dtype=torch.float64, device="cuda")
+    with pytest.raises(ifci.IfciError) as e:
+        plan.sigma(0, full)
+    assert e.value.code == 2
