@@ -162,7 +162,10 @@ ifci_status ifci_set_integrals(ifci_plan_t plan, const double* h, const double* 
  * (without the frozen-core energy and e_const).  c and sigma: device
  * [n_det] FP64, C[A][B] layout, any c (no symmetry needed); precision is
  * IFCI_FP64 or IFCI_MIXED (FP32 arithmetic, results widened to FP64).
- * Uses the workspace; c and sigma must not alias. */
+ * Uses the workspace; c and sigma must not alias.  Materialises E
+ * (npair x n_det); where the plan's workspace is sized only for the column
+ * path (half-filled 16-orbital increments, 180 GB of E otherwise) it returns
+ * IFCI_ERR_UNSUPPORTED: use ifci_sigma_sector there. */
 ifci_status ifci_sigma(ifci_plan_t plan, int64_t inc, const double* c, double* sigma,
                        int32_t precision, ifci_stream_t stream);
 
@@ -171,7 +174,7 @@ ifci_status ifci_sigma(ifci_plan_t plan, int64_t inc, const double* c, double* s
  * b (b + 1) / 2 + a, off-diagonal entries times sqrt 2), n_str (n_str + 1) / 2
  * FP64 each.  Increments that fit the batched solver (up to 8 active
  * orbitals) run as that solver computes sigma, in one workgroup; half-filled
- * increments of 10, 12 or 14 orbitals run the fused column kernel (one
+ * increments of 10, 12, 14 or 16 orbitals run the fused column kernel (one
  * workgroup per beta string, E never leaves LDS; uses the workspace).
  * Other shapes: IFCI_ERR_UNSUPPORTED.  c and sigma must not alias. */
 ifci_status ifci_sigma_sector(ifci_plan_t plan, int64_t inc, const double* c, double* sigma,
@@ -183,7 +186,13 @@ ifci_status ifci_sigma_sector(ifci_plan_t plan, int64_t inc, const double* c, do
  * [count] or NULL -- increments whose byte is nonzero are abandoned after one
  * iteration and reported EVICTED (failure injection); iters_out/resid_out:
  * device [count] or NULL.  Converged vectors stay in the workspace for
- * ifci_vector and ifci_rdm. */
+ * ifci_vector and ifci_rdm.  Increments that fit on chip run in one launch of
+ * the batched solver; the others (more than 8 active orbitals, or the plain
+ * solver) run device-wide, up to 8 at a time on streams the plan owns, each
+ * driven by a host thread: that work starts after what is already queued on
+ * `stream` and `stream` continues after it, so the call keeps stream order.
+ * The call returns when the device-wide solves have been issued (each waits
+ * on the host once per iteration). */
 ifci_status ifci_davidson(ifci_plan_t plan, int64_t first, int64_t count, double* e_out,
                           int32_t* status_out, const uint8_t* evict_mask, int32_t* iters_out,
                           double* resid_out, ifci_stream_t stream);
