@@ -33,7 +33,7 @@ struct IncDev {
   int64_t pair_off;  // int32 offset: pair table [n_str][npair], (J << 1 | neg) or -1
   int64_t link_off;  // int32 offset: compact links [n_str][n_link], (Q << 17 | J << 1 | neg)
   int64_t ord_off;   // int32 offset: ordered table [n_str][k*k]: E_pq|I> -> (J << 1 | neg) or -1
-  int64_t pairT_off; // int32 offset: pair table pair-major [npair][n_str], J + neg (n_str + 1), n_str: none
+  int64_t pairT_off; // int32 offset: pair table pair-major, int16 [npair][n_str], J + neg (n_str + 1), n_str: none
   int64_t int_off;   // double offset into the integral region
   int64_t vec_off;   // double offset into the Davidson region
 };

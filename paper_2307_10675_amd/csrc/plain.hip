@@ -254,7 +254,7 @@ __global__ void __launch_bounds__(256) col_frag_kernel(const double* __restrict_
 template <typename T, int K>
 __global__ void __launch_bounds__(col_threads<T>()) sigma_column_kernel(IncDev d, const double* __restrict__ V,
                                                                    const int32_t* __restrict__ ptab,
-                                                                   const int32_t* __restrict__ ptabT,
+                                                                   const int16_t* __restrict__ ptabT,
                                                                    const T* __restrict__ cf,
                                                                    const T* __restrict__ vfg,
                                                                    double* __restrict__ Sm) {
@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(col_threads<T>()) sigma_column_kernel(IncDev d
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       const int Q = 4 * s + kq;
-      ent[s] = Q < NP ? ptabT[Q * N + J] : N;
+      ent[s] = Q < NP ? (int)ptabT[Q * N + J] : N;
     }
     auto beta = [&](int s) -> T { return cf[(int64_t)browl[4 * s + kq] + jr]; };
 #pragma unroll
@@ -395,11 +395,14 @@ struct ColSplit {
   static constexpr int64_t lds = vf_bytes + col_bytes + s_bytes + brow_bytes;
 };
 
-constexpr int kSplitThreads = 512;  // two waves per SIMD: the single FP32 pass needs the registers
+// FP32: three waves per SIMD with a shorter load lookahead (fits the
+// registers of the single pass); FP64: two waves
+template <typename T>
+constexpr int split_threads() { return sizeof(T) == 4 ? 768 : 512; }
 
 template <typename T, int K>
-__global__ void __launch_bounds__(kSplitThreads) sigma_column_split_kernel(
-    IncDev d, const int32_t* __restrict__ ptab, const int32_t* __restrict__ ptabT, const T* __restrict__ cf,
+__global__ void __launch_bounds__(split_threads<T>()) sigma_column_split_kernel(
+    IncDev d, const int32_t* __restrict__ ptab, const int16_t* __restrict__ ptabT, const T* __restrict__ cf,
     const T* __restrict__ vfg, double* __restrict__ Sm) {
   typedef ColSplit<T, K> SH;
   typedef Mfma<T> M;
@@ -434,13 +437,13 @@ __global__ void __launch_bounds__(kSplitThreads) sigma_column_split_kernel(
       const int jr = 16 * t + col;
       const bool jv = jr < N;
       const int J = jv ? jr : N - 1;
-      constexpr int kBD = 8;  // loads run kBD k-steps ahead of their use
+      constexpr int kBD = sizeof(T) == 4 ? 6 : 8;  // loads run kBD k-steps ahead of their use
       int32_t ent[KS];
       T vb[KS], vaq[KS];
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
         const int Q = 4 * s + kq;
-        ent[s] = Q < NP ? ptabT[Q * N + J] : N;
+        ent[s] = Q < NP ? (int)ptabT[Q * N + J] : N;
       }
       auto beta = [&](int s) -> T { return cf[(int64_t)browl[4 * s + kq] + jr]; };
       // alpha value C[J1][b] signed, J1 + neg (N + 1) = ent (N: no link)
@@ -534,7 +537,7 @@ int64_t sigma_column_ws_doubles(const IncDev& d) {
 }
 
 template <typename T, int K>
-static hipError_t launch_column_k(const IncDev& d, const double* V, const int32_t* ptab, const int32_t* ptabT,
+static hipError_t launch_column_k(const IncDev& d, const double* V, const int32_t* ptab, const int16_t* ptabT,
                                   const double* c, double* sig, double* ws, double shift, hipStream_t st) {
   typedef ColShape<T, K> SH;
   static_assert(SH::lds <= kMaxLds, "column sigma LDS");
@@ -558,7 +561,7 @@ static hipError_t launch_column_k(const IncDev& d, const double* V, const int32_
 }
 
 template <typename T, int K>
-static hipError_t launch_column_split(const IncDev& d, const double* V, const int32_t* ptab, const int32_t* ptabT,
+static hipError_t launch_column_split(const IncDev& d, const double* V, const int32_t* ptab, const int16_t* ptabT,
                                       const double* c, double* sig, double* ws, double shift, hipStream_t st) {
   typedef ColSplit<T, K> SH;
   const int n = d.n_str;
@@ -572,7 +575,7 @@ static hipError_t launch_column_split(const IncDev& d, const double* V, const in
   hipLaunchKernelGGL((col_frag_kernel<T, K>), dim3((nfrag + 255) / 256), dim3(256), 0, st, V, shift, 2.0 * d.na,
                      vfg);
   hipLaunchKernelGGL((expand_sym_kernel<T>), dim3(4096), dim3(256), 0, st, d, c, cf);
-  hipLaunchKernelGGL((sigma_column_split_kernel<T, K>), dim3(n), dim3(kSplitThreads), (unsigned)SH::lds, st, d,
+  hipLaunchKernelGGL((sigma_column_split_kernel<T, K>), dim3(n), dim3(split_threads<T>()), (unsigned)SH::lds, st, d,
                      ptab, ptabT, (const T*)cf, (const T*)vfg, Sm);
   hipLaunchKernelGGL(sym_combine_kernel, dim3((unsigned)((d.n_sym + 255) / 256)), dim3(256), 0, st, d, Sm, sig);
   return hipGetLastError();
@@ -597,7 +600,7 @@ hipError_t prepare_sigma_wide() {
   return status;
 }
 
-static hipError_t launch_sigma_column(const IncDev& d, const double* V, const int32_t* ptab, const int32_t* ptabT,
+static hipError_t launch_sigma_column(const IncDev& d, const double* V, const int32_t* ptab, const int16_t* ptabT,
                                       const double* c, double* sig, double* ws, int precision, double shift,
                                       hipStream_t st) {
   if (prepare_sigma_wide() != hipSuccess) return hipErrorInvalidValue;
@@ -622,7 +625,7 @@ hipError_t launch_sigma_wide(const IncDev& d, const IncDev*, int, const double* 
   const int32_t* ptab = tables + d.pair_off;
   const int32_t* links = tables + d.link_off;
   if (mode == 1 && sigma_column_supported(d))
-    return launch_sigma_column(d, V, ptab, tables + d.pairT_off, c, sig, E, precision, shift, st);
+    return launch_sigma_column(d, V, ptab, (const int16_t*)(tables + d.pairT_off), c, sig, E, precision, shift, st);
   const int64_t tiles = (d.n_det + 63) / 64;
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 g1((unsigned)tiles), blk(kWideThreads);

@@ -85,16 +85,20 @@ ShapeTables build_shape(int k, int na, std::vector<int32_t>& blob) {
       }
     }
   }
-  // the same pair table pair-major, [npair][n_str], as an index into a
-  // column copy stored with its negation: J + neg (n_str + 1), n_str for no
-  // link (a zero entry after the last string).  A row of strings for one
-  // pair is contiguous (coalesced loads over 16 consecutive strings).
+  // the same pair table pair-major, [npair][n_str] of int16 (2 n_str + 1
+  // <= 25,741 at 16 orbitals), as an index into a column copy stored with
+  // its negation: J + neg (n_str + 1), n_str for no link (a zero entry after
+  // the last string).  A row of strings for one pair is contiguous
+  // (coalesced loads over 16 consecutive strings); int16 keeps the 16-orbital
+  // table (3.5 MB) within an L2.
   t.pairT_off = (int64_t)blob.size();
-  blob.resize(blob.size() + (size_t)t.n_str * t.npair, 0);
+  const int64_t nT = (int64_t)t.n_str * t.npair;
+  blob.resize(blob.size() + (size_t)((nT + 1) / 2), 0);
+  int16_t* pT = (int16_t*)(blob.data() + t.pairT_off);
   for (int I = 0; I < t.n_str; ++I)
     for (int Q = 0; Q < t.npair; ++Q) {
       const int32_t e = blob[t.pair_off + (int64_t)I * t.npair + Q];
-      blob[t.pairT_off + (int64_t)Q * t.n_str + I] = e < 0 ? t.n_str : (e >> 1) + (e & 1) * (t.n_str + 1);
+      pT[(int64_t)Q * t.n_str + I] = (int16_t)(e < 0 ? t.n_str : (e >> 1) + (e & 1) * (t.n_str + 1));
     }
   return t;
 }
