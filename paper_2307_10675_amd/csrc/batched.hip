@@ -13,6 +13,13 @@
 //   S[a][b]     = sum over the links of a of sign * E[Q][(J,b)];
 //   sigma       = S + S^T     (the beta part of sigma is the transpose of the
 //                              alpha part when C = C^T).
+// The MFMA rows P run over the off-diagonal pairs only.  A diagonal pair pp
+// links string a to itself when orbital p is occupied, so the diagonal rows
+// enter S[a][b] only as sum over p in a of E[pp][(a,b)] = sum_Q w_Q(a)
+// D[Q][(a,b)] with w_Q(a) = sum over p in a of V[pp][Q]: a per-string dot
+// product over the B operands already formed for the MFMA (one FMA per
+// operand), which at 8 orbitals saves the third 16-row tile (28 off-diagonal
+// pairs of 36).
 // Each wavefront owns one beta column b at a time: it computes E for the
 // whole column in its private LDS slice (stored transposed, E[a][P]) and
 // gathers S[:, b] from it, so no workgroup barrier sits inside the column
@@ -46,7 +53,7 @@ struct Lds {
   int32_t* ptab;   // int16 [n_str + 1][npair_pad] decoded pair table J | neg << 15, with
                    // J = n_str for no link (and for the sentinel last row and the
                    // padding pairs)
-  int32_t* links;  // [n_str][n_link]  (Q << 17 | J << 1 | neg)
+  int32_t* links;  // [n_str][n_link]  (o << 17 | J << 1 | neg), off-diagonal pairs o first
   int32_t* strs;   // [n_str]
   double* F;       // [n_str] string energies
   double* Jm;      // [k*k] (pp|qq)
@@ -99,14 +106,25 @@ __host__ __device__ inline int64_t persistent_bytes(int k, int n_str, int n_link
 __host__ __device__ inline int64_t transient_bytes(int n_str) {
   return a16(8 * tri(n_str)) + 8 * (256 + 256 + 16 + 16 + 16) + 4 * 16 + 8 * 32 + 4 * 16 + 16 + 8 * 16 * 24;
 }
-// E slice of one wave, transposed: E[a][P] for one column, 16-string tiles
-// of the longest column by an odd row stride of at least 17 (npair | 1), and
-// a spare tail for the padding rows of the last MFMA tile.  With a stride of
-// at least 16 the padding rows P >= npair of the last row tile reach only
-// into the first 16 (MT - 1) entries of the next string's row.
+// E slice of one wave, transposed: E[a][o] for one column and the
+// off-diagonal pairs o, 16-string tiles of the longest column by an odd row
+// stride of at least 17 (n_off | 1), and a spare tail for the padding rows of
+// the last MFMA tile.  With a stride of at least 16 the padding rows
+// o >= n_off of the last row tile reach only into the first 16 (MT - 1)
+// entries of the next string's row.
 __host__ __device__ constexpr int slice_rows(int k) { return (max_strings(k) + 15) / 16 * 16; }
 __host__ __device__ constexpr int slice_stride(int k) {
-  return ((k * (k + 1) / 2) | 1) > 17 ? ((k * (k + 1) / 2) | 1) : 17;
+  return ((k * (k - 1) / 2) | 1) > 17 ? ((k * (k - 1) / 2) | 1) : 17;
+}
+// Row stride of the diagonal-pair weight table w[Q][a] (the strings of the
+// longest column): 16 mod 32, so the 32 lanes of a half wave (16 strings x 2
+// pairs) read distinct banks.
+__host__ __device__ constexpr int wt_stride(int k) { return slice_rows(k) | 16; }
+// Weight table w[npair_pad][wt_stride] and the diagonal rows u[k][npair_pad]
+// of V it is summed from, of T, at the start of the sigma scratch (ahead of
+// the E slices).
+__host__ __device__ inline int64_t wt_bytes(int k, int elem) {
+  return a16((int64_t)npair_pad(k) * wt_stride(k) * elem) + a16((int64_t)k * npair_pad(k) * elem);
 }
 // Entry rows * stride + 16 is kept zero: absent links read it.
 __host__ __device__ inline int64_t et_slice_bytes(int k, int, int elem) {
@@ -185,7 +203,9 @@ template <typename T, int K>
 __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, const double* __restrict__ V,
                                              double shift, int et_waves) {
   constexpr int NP = K * (K + 1) / 2;
-  constexpr int MT = (NP + 15) / 16;
+  constexpr int NO = K * (K - 1) / 2;       // off-diagonal pairs: the MFMA rows
+  constexpr int MT = (NO + 15) / 16;        // 0 at one orbital
+  constexpr int MTA = MT > 0 ? MT : 1;      // array extent
   constexpr int KS = (NP + 3) / 4;
   typedef Mfma<T> M;
   // bit P set for the diagonal pairs P = i (i + 3) / 2 (the pair (i, i))
@@ -196,30 +216,64 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
   }();
   static_assert(NP <= 64, "pair mask holds 64 pairs");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int n = d.n_str, nlink = d.n_link;
+  const int n = d.n_str, nlink = d.n_link - d.na;  // off-diagonal links per string
+  const int lstride = d.n_link;                     // row stride of the link table
   const T* cp = (const T*)L.cp;
   const double nel = 2.0 * d.na;
   const double sh = nel > 0.0 ? shift / (nel * nel) : 0.0;
+  constexpr int NPp = 4 * KS;
+  constexpr int WS = wt_stride(K);
 
-  // A fragments: V[16 m + lane % 16][4 s + lane / 16]
-  T afr[MT][KS];
+  // Diagonal-pair weights w[Q][a] = sum over the orbitals p of string a of
+  // V[pp][Q] (shifted in the diagonal block), summed in a fixed order from
+  // the rows u[p][Q]; zero for padding pairs and strings a >= n.
+  T* const wt = (T*)L.et;
+  T* const ut = (T*)(L.et + a16((int64_t)NPp * WS * (int64_t)sizeof(T)));
+  for (int i = threadIdx.x; i < K * NPp; i += blockDim.x) {
+    const int p = i / NPp, Q = i - p * NPp;
+    double v = 0.0;
+    if (Q < NP) {
+      v = V[(p * (p + 3) / 2) * NP + Q];
+      if ((kDiagPairs >> Q) & 1) v -= sh;
+    }
+    ut[i] = (T)v;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < NPp * WS; i += blockDim.x) {
+    const int Q = i / WS, a = i - Q * WS;
+    T v = (T)0;
+    if (a < n && Q < NP) {
+      uint32_t occ = (uint32_t)L.strs[a];
+      while (occ) {
+        const int p = __builtin_ctz(occ);
+        occ &= occ - 1u;
+        v += ut[p * NPp + Q];
+      }
+    }
+    wt[i] = v;
+  }
+  __syncthreads();
+
+  // A fragments: V[P(16 m + lane % 16)][4 s + lane / 16] for the off-diagonal
+  // pair P(o) = o + p of row o (p the larger orbital of the pair)
+  T afr[MTA][KS];
   {
     const int r = lane & 15, c = lane >> 4;
 #pragma unroll
-    for (int m = 0; m < MT; ++m)
+    for (int m = 0; m < MTA; ++m)
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        const int P = 16 * m + r, Q = 4 * s + c;
+        const int o = 16 * m + r, Q = 4 * s + c;
         double v = 0.0;
-        if (P < NP && Q < NP) {
-          v = V[P * NP + Q];
-          if ((kDiagPairs >> P) & (kDiagPairs >> Q) & 1) v -= sh;
+        if (m < MT && o < NO && Q < NP) {
+          int p = 1;
+          while (p * (p + 1) / 2 <= o) ++p;
+          v = V[(o + p) * NP + Q];
         }
         afr[m][s] = (T)v;
       }
   }
   if (wave >= et_waves) return;
-  constexpr int NPp = 4 * KS;
   constexpr int NTM = slice_rows(K) / 16;  // 16-string tiles of the longest column
   constexpr int NS = slice_stride(K);      // E slice row stride (odd, >= 17)
   static_assert(NS >= 16 && 16 * MT - NS <= NS, "padding rows must stay within the next row's first tiles");
@@ -227,7 +281,8 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
   const int nt_count = (n + 15) / 16;
   const int kq = lane >> 4, col = lane & 15;
   const int ld = n + 1;
-  T* et = (T*)(L.et + (size_t)wave * et_slice_bytes(K, n, (int)sizeof(T)));
+  T* et = (T*)(L.et + wt_bytes(K, (int)sizeof(T)) + (size_t)wave * et_slice_bytes(K, n, (int)sizeof(T)));
+  const T* const wl = wt + kq * WS + col;  // this lane's w[4 s + kq][16 t + col] at compile-time offsets
   const int16_t* pt = (const int16_t*)L.ptab;  // [a][Q]: J | neg << 15, J = n: none
   T* colb = (T*)L.colb + (size_t)wave * 2 * ld;
   const uint32_t colb_off = (uint32_t)((const char*)colb - L.root);
@@ -265,15 +320,15 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
   // links per lane, summed over the 8 lanes of a string in a fixed tree.
   // FP32 keeps the codes in registers for every column; FP64 has no
   // registers to spare and decodes them per column.
-  constexpr int LM = ((K + 1) / 2) * ((K + 2) / 2);  // max of na (K - na + 1)
-  constexpr int LP = (LM + 1) / 2;
+  constexpr int LM = (K / 2) * ((K + 1) / 2);  // max of na (K - na): off-diagonal links
+  constexpr int LP = LM > 0 ? (LM + 1) / 2 : 1;
   constexpr bool kTwoPass = max_strings(K) > 64;
   static_assert(!kTwoPass || (LM <= 24 && max_strings(K) <= 64 + 8), "pass 1 covers 8 strings of 24 links");
   constexpr int ZI = slice_rows(K) * NS + 16;  // zero entry of the slice
   constexpr bool kLinkRegs = kFull;
   auto code_of = [&](int a, int l) -> uint32_t {
     if (a < n && l < nlink) {
-      const int code = L.links[a * nlink + l];
+      const int code = L.links[a * lstride + l];
       return (uint32_t)(((code >> 1) & 0xFFFF) * NS + (code >> 17)) | ((uint32_t)(code & 1) << 15);
     }
     return (uint32_t)ZI;
@@ -323,6 +378,8 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
   for (int b = wave; b < n; b += et_waves) {
+    // diagonal-pair part of S[:, b]: string lane (pass 0), string 64 + lane / 8 (pass 1)
+    T dext0 = (T)0, dext1 = (T)0;
     // Keep the packed offsets packed: without this the compiler unpacks
     // them once before the loop into twice as many registers and spills.
 #pragma unroll
@@ -340,38 +397,46 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
     // E[:, (a, b)] for C consecutive 16-string tiles from tile t on (C
     // independent MFMA chains per row tile), stored transposed into the
     // wave's slice.  Rows a >= n of the slice are padding.  The last MFMA
-    // row tile holds rows P >= npair (zero) that spill into the next
+    // row tile holds rows o >= n_off (zero) that spill into the next
     // string's row: it is stored first, so the other tiles overwrite what it
-    // spilled.
+    // spilled.  Beside the MFMAs each lane accumulates w[Q][a] D[Q][(a, b)]
+    // over its pairs Q = 4 s + kq: the diagonal-pair part of S[a][b] once
+    // summed over the four k-lanes.
     auto tiles = [&](auto tt, auto cnt) {
       constexpr int t = decltype(tt)::value;
       constexpr int C = decltype(cnt)::value;
-      typename M::acc acc[C][MT];
+      typename M::acc acc[C][MTA];
 #pragma unroll
       for (int c = 0; c < C; ++c)
 #pragma unroll
-        for (int m = 0; m < MT; ++m) acc[c][m] = M::zero();
+        for (int m = 0; m < MTA; ++m) acc[c][m] = M::zero();
       auto alpha = [&](int tt2, int s) -> T {
         const int i = tt2 * KS + s;
         return *(const T*)(L.root + ((ia[i >> 1] >> (16 * (i & 1))) & 0xFFFFu));
       };
       // loads of step s + 1 are issued ahead of the MFMAs of step s
-      T va[C], vb[C];
+      T va[C], vb[C], wv[C], dsum[C];
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         va[c] = alpha(t + c, 0);
         vb[c] = beta(t + c, 0);
+        wv[c] = wl[16 * (t + c)];
+        dsum[c] = (T)0;
       }
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
         T bo[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) bo[c] = fma_t(sg[s], vb[c], va[c]);
+        for (int c = 0; c < C; ++c) {
+          bo[c] = fma_t(sg[s], vb[c], va[c]);
+          dsum[c] = fma_t(wv[c], bo[c], dsum[c]);
+        }
         if (s + 1 < KS) {
 #pragma unroll
           for (int c = 0; c < C; ++c) {
             va[c] = alpha(t + c, s + 1);
             vb[c] = beta(t + c, s + 1);
+            wv[c] = wl[4 * (s + 1) * WS + 16 * (t + c)];
           }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -380,6 +445,19 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
 #pragma unroll
           for (int c = 0; c < C; ++c) acc[c][m] = M::mma(afr[m][s], bo[c], acc[c][m]);
         __builtin_amdgcn_sched_barrier(0);
+      }
+      // the diagonal-pair sums of string 16 (t + c) + col, summed over the
+      // k-lanes, to the gather lane of that string
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        T v = dsum[c];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        if (t + c < 4) {
+          if ((lane >> 4) == t + c) dext0 = v;
+        } else {
+          dext1 = __shfl(v, lane >> 3);
+        }
       }
 #pragma unroll
       for (int mm = 0; mm < MT; ++mm) {
@@ -427,7 +505,7 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
       // all loads in flight before the first use (left alone, the compiler
       // trades them for registers and waits on each load in turn)
       __builtin_amdgcn_sched_barrier(0);
-      T sum = (T)0;
+      T sum = dext0;
 #pragma unroll
       for (int l = 0; l < 2 * LP; ++l) sum += ((lk0[l >> 1] >> (16 * (l & 1))) & 0x8000u) ? -v[l] : v[l];
       if (lane < n) lds_add(&L.sp[pk32(lane, b)], (lane == b ? 2.0 : kSqrt2) * (double)sum);
@@ -440,6 +518,7 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
       sum += __shfl_down(sum, 4);
       sum += __shfl_down(sum, 2);
       sum += __shfl_down(sum, 1);
+      sum += dext1;  // one lane of the eight: the lane the sum lands on
       if ((lane & 7) == 0 && a1 < n) lds_add(&L.sp[pk32(a1, b)], (a1 == b ? 2.0 : kSqrt2) * (double)sum);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -448,7 +527,7 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
   }
 }
 
-// Pair table (decoded, see Lds::ptab) and link lists into LDS.
+// Pair table (decoded, see Lds::ptab), strings and link lists into LDS.
 __device__ inline void load_tables(const IncDev& d, const Lds& L, const int32_t* __restrict__ tables) {
   const int n = d.n_str, np = d.npair;
   const int npp = npair_pad(d.k);
@@ -459,7 +538,24 @@ __device__ inline void load_tables(const IncDev& d, const Lds& L, const int32_t*
     const int J = e < 0 ? n : (e >> 1), neg = e < 0 ? 0 : (e & 1);
     pt[i] = (int16_t)(J | (neg << 15));
   }
-  for (int i = threadIdx.x; i < n * d.n_link; i += blockDim.x) L.links[i] = tables[d.link_off + i];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) L.strs[i] = tables[d.str_off + i];
+  // links of each string without its diagonal pairs (carried by the
+  // per-string dot product of sigma_sector), the pair Q = p (p + 1) / 2 + q
+  // (p > q) renumbered to its off-diagonal index o = Q - p; the na(k - na)
+  // entries first, the rest unused
+  const int nl = d.n_link;
+  for (int a = threadIdx.x; a < n; a += blockDim.x) {
+    int m = 0;
+    for (int l = 0; l < nl; ++l) {
+      const int code = tables[d.link_off + a * nl + l];
+      const int Q = code >> 17;
+      int p = 0;
+      while ((p + 1) * (p + 2) / 2 <= Q) ++p;
+      if (Q - p * (p + 1) / 2 == p) continue;
+      L.links[a * nl + m++] = ((Q - p) << 17) | (code & 0x1FFFF);
+    }
+    for (; m < nl; ++m) L.links[a * nl + m] = 0;
+  }
 }
 
 // Expand the packed scaled vector tv into the unscaled cp of type T (FP32
@@ -525,7 +621,7 @@ __device__ inline void sigma_phase(const IncDev& d, const Lds& L, const double* 
 template <typename T, int K>
 __device__ inline int et_waves_for(const IncDev& d, const Lds& L) {
   const int64_t slice = et_slice_bytes(K, d.n_str, (int)sizeof(T));
-  int w = (int)(L.et_total / slice);
+  int w = (int)((L.et_total - wt_bytes(K, (int)sizeof(T))) / slice);
   const int wc = (int)(colb_bytes(d.n_str) / (2 * (int64_t)(d.n_str + 1) * (int64_t)sizeof(T)));
   w = w < wc ? w : wc;
   const int nw = blockDim.x >> 6;
@@ -538,7 +634,6 @@ __device__ inline void load_increment(const IncDev& d, const Lds& L, const int32
   const int n = d.n_str, np = d.npair, k = d.k;
   const IntBlock ib = int_block(k);
   load_tables(d, L, tables);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) L.strs[i] = tables[d.str_off + i];
   for (int i = threadIdx.x; i < k * k; i += blockDim.x) {
     L.Jm[i] = B[ib.J + i];
     L.Km[i] = B[ib.K + i];
@@ -1393,12 +1488,12 @@ __global__ void __launch_bounds__(kBatchThreads) sigma_one_kernel(const IncDev* 
 // LDS the batched solver needs for an increment: the persistent part plus
 // the larger of the transient part and one FP64 E slice.
 int64_t batched_lds_bytes(int k, int n_str, int n_link) {
-  const int64_t tr = transient_bytes(n_str), sl = et_slice_bytes(k, n_str, 8);
+  const int64_t tr = transient_bytes(n_str), sl = wt_bytes(k, 8) + et_slice_bytes(k, n_str, 8);
   return persistent_bytes(k, n_str, n_link) + (tr > sl ? tr : sl);
 }
 // LDS that gives every wave of the workgroup its FP64 E slice.
 int64_t batched_lds_want(int k, int n_str, int n_link) {
-  const int64_t tr = transient_bytes(n_str), sl = (kBatchThreads / 64) * et_slice_bytes(k, n_str, 8);
+  const int64_t tr = transient_bytes(n_str), sl = wt_bytes(k, 8) + (kBatchThreads / 64) * et_slice_bytes(k, n_str, 8);
   return persistent_bytes(k, n_str, n_link) + (tr > sl ? tr : sl);
 }
 
