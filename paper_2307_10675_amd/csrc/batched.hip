@@ -187,6 +187,12 @@ __device__ inline Lds carve(char* base, const IncDev& d, int lds_bytes) {
   return L;
 }
 
+// Byte offset from L.et of the diagonal-pair weight table of element size
+// elem: the last wt_bytes of the scratch region (16-byte aligned).
+__device__ inline int64_t wt_offset(const Lds& L, int k, int elem) {
+  return ((int64_t)L.et_total - wt_bytes(k, elem)) & ~(int64_t)15;
+}
+
 // 32-bit packed index of (x, y) in the upper triangle (at most 70 strings here).
 __device__ __forceinline__ int pk32(int x, int y) {
   return x <= y ? ((y * (y + 1)) >> 1) + x : ((x * (x + 1)) >> 1) + y;
@@ -201,7 +207,7 @@ __device__ __forceinline__ int pk32(int x, int y) {
 // = shift from the operator.
 template <typename T, int K>
 __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, const double* __restrict__ V,
-                                             double shift, int et_waves) {
+                                             double shift, int et_waves, bool build_w) {
   constexpr int NP = K * (K + 1) / 2;
   constexpr int NO = K * (K - 1) / 2;       // off-diagonal pairs: the MFMA rows
   constexpr int MT = (NO + 15) / 16;        // 0 at one orbital
@@ -226,9 +232,13 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
 
   // Diagonal-pair weights w[Q][a] = sum over the orbitals p of string a of
   // V[pp][Q] (shifted in the diagonal block), summed in a fixed order from
-  // the rows u[p][Q]; zero for padding pairs and strings a >= n.
-  T* const wt = (T*)L.et;
-  T* const ut = (T*)(L.et + a16((int64_t)NPp * WS * (int64_t)sizeof(T)));
+  // the rows u[p][Q]; zero for padding pairs and strings a >= n.  They sit
+  // at the end of the scratch region, which neither the E slices nor the
+  // solver's transient data reach, so a caller that keeps V, the shift and
+  // T builds them once (build_w) and reuses them for later sigmas.
+  T* const wt = (T*)(L.et + wt_offset(L, K, (int)sizeof(T)));
+  T* const ut = (T*)((char*)wt + a16((int64_t)NPp * WS * (int64_t)sizeof(T)));
+  if (build_w) {
   for (int i = threadIdx.x; i < K * NPp; i += blockDim.x) {
     const int p = i / NPp, Q = i - p * NPp;
     double v = 0.0;
@@ -253,6 +263,7 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
     wt[i] = v;
   }
   __syncthreads();
+  }
 
   // A fragments: V[P(16 m + lane % 16)][4 s + lane / 16] for the off-diagonal
   // pair P(o) = o + p of row o (p the larger orbital of the pair)
@@ -281,7 +292,7 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
   const int nt_count = (n + 15) / 16;
   const int kq = lane >> 4, col = lane & 15;
   const int ld = n + 1;
-  T* et = (T*)(L.et + wt_bytes(K, (int)sizeof(T)) + (size_t)wave * et_slice_bytes(K, n, (int)sizeof(T)));
+  T* et = (T*)(L.et + (size_t)wave * et_slice_bytes(K, n, (int)sizeof(T)));
   const T* const wl = wt + kq * WS + col;  // this lane's w[4 s + kq][16 t + col] at compile-time offsets
   const int16_t* pt = (const int16_t*)L.ptab;  // [a][Q]: J | neg << 15, J = n: none
   T* colb = (T*)L.colb + (size_t)wave * 2 * ld;
@@ -612,16 +623,16 @@ __device__ __forceinline__ void stage_entry(const IncDev& d, const Lds& L, int i
 // synchronised; otherwise they are built here from L.tv.
 template <typename T, int K>
 __device__ inline void sigma_phase(const IncDev& d, const Lds& L, const double* V, double shift,
-                                   int et_waves, bool staged = false) {
+                                   int et_waves, bool staged = false, bool build_w = true) {
   if (!staged) prepare_sigma<T>(d, L);
-  sigma_sector<T, K>(d, L, V, shift, et_waves);
+  sigma_sector<T, K>(d, L, V, shift, et_waves, build_w);
   __syncthreads();
 }
 
 template <typename T, int K>
 __device__ inline int et_waves_for(const IncDev& d, const Lds& L) {
   const int64_t slice = et_slice_bytes(K, d.n_str, (int)sizeof(T));
-  int w = (int)((L.et_total - wt_bytes(K, (int)sizeof(T))) / slice);
+  int w = (int)(wt_offset(L, K, (int)sizeof(T)) / slice);
   const int wc = (int)(colb_bytes(d.n_str) / (2 * (int64_t)(d.n_str + 1) * (int64_t)sizeof(T)));
   w = w < wc ? w : wc;
   const int nw = blockDim.x >> 6;
@@ -1142,14 +1153,16 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
   bool staged = false;   // cp / sp already hold the next sigma's input
   bool fresh = true;     // x has no sigma yet (start or precision switch)
   bool have_p = false;
+  bool w_built = false;  // the diagonal-pair weights of the current precision are in LDS
   double xap = 0.0, pap = 0.0;  // x.Ap and p.Ap of the current basis
 
   while (true) {
     // ---- sigma of the vector in L.tv (x when fresh, else w)
     if (phase == 32)
-      sigma_phase<float, K>(d, L, Vm, E0, ew32, staged);
+      sigma_phase<float, K>(d, L, Vm, E0, ew32, staged, !w_built);
     else
-      sigma_phase<double, K>(d, L, Vm, E0, ew64, staged);
+      sigma_phase<double, K>(d, L, Vm, E0, ew64, staged, !w_built);
+    w_built = true;
     staged = false;
     ++iters;
     IFCI_MARK(kPhSigma);
@@ -1321,6 +1334,7 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
       if (phase == 32) {
         // FP64 refinement: sigma of x in FP64, then continue in FP64
         phase = 64;
+        w_built = false;
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
           const int i = tix + e * kBatchThreads;
@@ -1488,13 +1502,13 @@ __global__ void __launch_bounds__(kBatchThreads) sigma_one_kernel(const IncDev* 
 // LDS the batched solver needs for an increment: the persistent part plus
 // the larger of the transient part and one FP64 E slice.
 int64_t batched_lds_bytes(int k, int n_str, int n_link) {
-  const int64_t tr = transient_bytes(n_str), sl = wt_bytes(k, 8) + et_slice_bytes(k, n_str, 8);
-  return persistent_bytes(k, n_str, n_link) + (tr > sl ? tr : sl);
+  const int64_t tr = transient_bytes(n_str), sl = et_slice_bytes(k, n_str, 8);
+  return persistent_bytes(k, n_str, n_link) + (tr > sl ? tr : sl) + wt_bytes(k, 8) + 16;
 }
 // LDS that gives every wave of the workgroup its FP64 E slice.
 int64_t batched_lds_want(int k, int n_str, int n_link) {
-  const int64_t tr = transient_bytes(n_str), sl = wt_bytes(k, 8) + (kBatchThreads / 64) * et_slice_bytes(k, n_str, 8);
-  return persistent_bytes(k, n_str, n_link) + (tr > sl ? tr : sl);
+  const int64_t tr = transient_bytes(n_str), sl = (kBatchThreads / 64) * et_slice_bytes(k, n_str, 8);
+  return persistent_bytes(k, n_str, n_link) + (tr > sl ? tr : sl) + wt_bytes(k, 8) + 16;
 }
 
 hipError_t launch_batched(const SolveArgs& A, int lds_bytes, hipStream_t st) {
