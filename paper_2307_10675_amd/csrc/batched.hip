@@ -123,8 +123,16 @@ __host__ __device__ constexpr int wt_stride(int k) { return slice_rows(k) | 16; 
 // Weight table w[npair_pad][wt_stride] and the diagonal rows u[k][npair_pad]
 // of V it is summed from, of T, at the start of the sigma scratch (ahead of
 // the E slices).
+// FP32 A fragments of the off-diagonal rows of V in lane order,
+// [MT][KS][64] floats (FP64 reads its fragments from V for each sigma: the
+// FP64 copy would cost an E slice at 8 orbitals).
+__host__ __device__ inline int64_t afr_bytes(int k, int elem) {
+  const int mt = (k * (k - 1) / 2 + 15) / 16;
+  return elem == 4 ? a16((int64_t)(mt > 0 ? mt : 1) * (npair_pad(k) / 4) * 64 * elem) : 0;
+}
 __host__ __device__ inline int64_t wt_bytes(int k, int elem) {
-  return a16((int64_t)npair_pad(k) * wt_stride(k) * elem) + a16((int64_t)k * npair_pad(k) * elem);
+  return a16((int64_t)npair_pad(k) * wt_stride(k) * elem) + a16((int64_t)k * npair_pad(k) * elem) +
+         afr_bytes(k, elem);
 }
 // Entry rows * stride + 16 is kept zero: absent links read it.
 __host__ __device__ inline int64_t et_slice_bytes(int k, int, int elem) {
@@ -238,7 +246,26 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
   // T builds them once (build_w) and reuses them for later sigmas.
   T* const wt = (T*)(L.et + wt_offset(L, K, (int)sizeof(T)));
   T* const ut = (T*)((char*)wt + a16((int64_t)NPp * WS * (int64_t)sizeof(T)));
+  // A fragments: V[P(16 m + lane % 16)][4 s + lane / 16] for the off-diagonal
+  // pair P(o) = o + p of row o (p the larger orbital of the pair); FP32
+  // stores them in lane order beside the weights, built with them
+  constexpr bool kAfrLds = sizeof(T) == 4;
+  T* const afl = (T*)((char*)ut + a16((int64_t)K * NPp * (int64_t)sizeof(T)));
+  auto afr_value = [&](int m, int sq, int ln) -> T {
+    const int o = 16 * m + (ln & 15), Q = 4 * sq + (ln >> 4);
+    double v = 0.0;
+    if (m < MT && o < NO && Q < NP) {
+      int p = 1;
+      while (p * (p + 1) / 2 <= o) ++p;
+      v = V[(o + p) * NP + Q];
+    }
+    return (T)v;
+  };
   if (build_w) {
+  for (int i = threadIdx.x; kAfrLds && i < MTA * KS * 64; i += blockDim.x) {
+    const int ms = i >> 6, m = ms / KS;
+    afl[i] = afr_value(m, ms - m * KS, i & 63);
+  }
   for (int i = threadIdx.x; i < K * NPp; i += blockDim.x) {
     const int p = i / NPp, Q = i - p * NPp;
     double v = 0.0;
@@ -265,26 +292,12 @@ __device__ __forceinline__ void sigma_sector(const IncDev& d, const Lds& L, cons
   __syncthreads();
   }
 
-  // A fragments: V[P(16 m + lane % 16)][4 s + lane / 16] for the off-diagonal
-  // pair P(o) = o + p of row o (p the larger orbital of the pair)
-  T afr[MTA][KS];
-  {
-    const int r = lane & 15, c = lane >> 4;
-#pragma unroll
-    for (int m = 0; m < MTA; ++m)
-#pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const int o = 16 * m + r, Q = 4 * s + c;
-        double v = 0.0;
-        if (m < MT && o < NO && Q < NP) {
-          int p = 1;
-          while (p * (p + 1) / 2 <= o) ++p;
-          v = V[(o + p) * NP + Q];
-        }
-        afr[m][s] = (T)v;
-      }
-  }
   if (wave >= et_waves) return;
+  T afr[MTA][KS];
+#pragma unroll
+  for (int m = 0; m < MTA; ++m)
+#pragma unroll
+    for (int s = 0; s < KS; ++s) afr[m][s] = kAfrLds ? afl[(m * KS + s) * 64 + lane] : afr_value(m, s, lane);
   constexpr int NTM = slice_rows(K) / 16;  // 16-string tiles of the longest column
   constexpr int NS = slice_stride(K);      // E slice row stride (odd, >= 17)
   static_assert(NS >= 16 && 16 * MT - NS <= NS, "padding rows must stay within the next row's first tiles");
