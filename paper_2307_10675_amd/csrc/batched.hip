@@ -636,10 +636,10 @@ __device__ __forceinline__ void stage_entry(const IncDev& d, const Lds& L, int i
 // synchronised; otherwise they are built here from L.tv.
 template <typename T, int K>
 __device__ inline void sigma_phase(const IncDev& d, const Lds& L, const double* V, double shift,
-                                   int et_waves, bool staged = false, bool build_w = true) {
+                                   int et_waves, bool staged = false, bool build_w = true, bool sync = true) {
   if (!staged) prepare_sigma<T>(d, L);
   sigma_sector<T, K>(d, L, V, shift, et_waves, build_w);
-  __syncthreads();
+  if (sync) __syncthreads();
 }
 
 template <typename T, int K>
@@ -1172,13 +1172,12 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
   while (true) {
     // ---- sigma of the vector in L.tv (x when fresh, else w)
     if (phase == 32)
-      sigma_phase<float, K>(d, L, Vm, E0, ew32, staged, !w_built);
+      sigma_phase<float, K>(d, L, Vm, E0, ew32, staged, !w_built, false);
     else
-      sigma_phase<double, K>(d, L, Vm, E0, ew64, staged, !w_built);
+      sigma_phase<double, K>(d, L, Vm, E0, ew64, staged, !w_built, false);
     w_built = true;
     staged = false;
     ++iters;
-    IFCI_MARK(kPhSigma);
     // ---- this thread's NE entries of x, w, p, Ax, Ap and the diagonal, in
     // registers for the whole non-sigma part of the iteration (one round of
     // loads; sigma(w) is read from L.sp)
@@ -1191,6 +1190,9 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
     // registers
     int tix = tid;
     asm volatile("" : "+v"(tix));
+    // (issued before the barrier that ends sigma: a wave that has finished
+    // its columns loads while the others still contract; each thread reads
+    // only entries it wrote itself)
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
       const int i = min(tix + e * kBatchThreads, nsi - 1);
@@ -1200,8 +1202,11 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
       rax[e] = base[mst + i];
       rap[e] = base[mst + 2 * sti + i];
       rhd[e] = base[2 * mst + i];
-      rs[e] = L.sp[i];
     }
+    __syncthreads();
+    IFCI_MARK(kPhSigma);
+#pragma unroll
+    for (int e = 0; e < NE; ++e) rs[e] = L.sp[min(tix + e * kBatchThreads, nsi - 1)];
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
       const bool in = tid + e * kBatchThreads < nsi;
