@@ -103,3 +103,30 @@ def test_sigma_sector_rejects_large(plan):
     with pytest.raises(ifci.IfciError) as e:
         p.sigma_sector(0, c)
     assert e.value.code == 2
+
+
+# Odd orbital counts and fillings away from half: 1-orbital increments (no
+# off-diagonal pair, no MFMA row tile), 3- and 6-orbital ones with one or two
+# electrons per spin per body.
+ODD = [
+    ("1o", dict(n_bodies=3, orbs_per_body=1, nocc_per_body=1, order=3, seed=301)),
+    ("3o1e", dict(n_bodies=3, orbs_per_body=3, nocc_per_body=1, order=2, seed=302)),
+    ("3o2e", dict(n_bodies=2, orbs_per_body=3, nocc_per_body=2, order=2, seed=303)),
+]
+
+
+@pytest.mark.parametrize("name,kw", ODD, ids=[n for n, _ in ODD])
+def test_sigma_sector_odd_shapes(name, kw):
+    import torch
+    print(f"[sigma] odd shapes {name}", flush=True)
+    p = synthetic.chain(**kw)
+    plan = ifci.Plan(p).attach(p.h, p.eri)
+    for i, inc in enumerate(plan.increments()):
+        H, n_str, _ = active_hamiltonian(p, inc.bodies)
+        c = synthetic.random_vector(H.shape[0], 10 + i, symmetric_dim=n_str)
+        want = H @ c
+        scale = np.abs(H).max() * np.abs(c).sum()
+        got = plan.sigma_sector(i, torch.tensor(c, device="cuda")).cpu().numpy()
+        assert np.abs(got - want).max() <= 1e-12 * scale, (name, inc.bodies, np.abs(got - want).max())
+        got32 = plan.sigma_sector(i, torch.tensor(c, device="cuda"), precision=ifci.MIXED).cpu().numpy()
+        assert np.abs(got32 - want).max() <= 2e-6 * scale, (name, inc.bodies, np.abs(got32 - want).max())
