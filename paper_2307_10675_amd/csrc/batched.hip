@@ -811,13 +811,15 @@ __device__ __forceinline__ void solve_one(const SolveArgs& A, int pos, char* lds
   const int64_t o = (int64_t)id - A.first;  // position in the caller's range
   const bool evict = A.evict && A.evict[o] != 0;
   const int keep = mmax / 2 < kKeep ? mmax / 2 : kKeep;
+  bool w_built = false;  // the diagonal-pair weights of the current precision are in LDS
 
   while (true) {
     // sigma of the newest basis vector (in L.tv) -> S[m]
     if (phase == 32)
-      sigma_phase<float, K>(d, L, Vm, E0, ew32);
+      sigma_phase<float, K>(d, L, Vm, E0, ew32, false, !w_built);
     else
-      sigma_phase<double, K>(d, L, Vm, E0, ew64);
+      sigma_phase<double, K>(d, L, Vm, E0, ew64, false, !w_built);
+    w_built = true;
     ++iters;
     for (int64_t i = tid; i < ns; i += blockDim.x) Sb[m * st + i] = L.sp[i];
     IFCI_MARK(kPhSigma);
@@ -892,6 +894,7 @@ __device__ __forceinline__ void solve_one(const SolveArgs& A, int pos, char* lds
       if (phase == 32) {
         // FP64 refinement: restart from x with FP64 sigma
         phase = 64;
+        w_built = false;
         for (int64_t i = tid; i < ns; i += blockDim.x) {
           const double x = X[i];
           L.tv[i] = x;
