@@ -1066,7 +1066,9 @@ __device__ inline void small_eig3(const double g[3][3], double* theta, double z[
     const double pv = ((l + c2) * l + c1) * l + c0;
     const double dv = (3.0 * l + 2.0 * c2) * l + c1;
     if (!(dv > 0.0)) break;
-    const double step = pv / dv;
+    // the hardware reciprocal is accurate enough for a Newton step (the
+    // iteration still ends at the root) and shortens the dependent chain
+    const double step = pv * __builtin_amdgcn_rcp(dv);
     l -= step;
     if (fabs(step) <= 1e-15 * scale) break;
   }
