@@ -38,7 +38,9 @@
 // LDS holds a persistent part (tables, subspace matrix and its eigenvectors,
 // the CI vector and the sigma accumulator) and a transient part (working
 // vector, eigensolver scratch, reduction buffers) that the per-wave E slices
-// overlay while sigma runs.
+// overlay while sigma runs.  The end of the transient region, beyond both,
+// holds the diagonal-pair weights and (FP32) the A fragments of V, which the
+// solvers build once per increment and precision.
 #include <type_traits>
 
 #include "device_common.hpp"
