@@ -174,10 +174,11 @@ __global__ void __launch_bounds__(kWideThreads) gather_sym_kernel(IncDev d, cons
 // addresses both the signed C value and the signed accumulator slot (S is
 // the first half minus the second).  FP64 sums of the FP32 products make S
 // practically independent of the atomic order.
-// FP32 runs three waves per SIMD (more waves hide the loads and VALU work
-// beside the MFMAs; four leave too few registers), FP64 two.
+// Both precisions run three waves per SIMD (more waves hide the loads and
+// VALU work beside the MFMAs; four leave too few registers; FP64 with three
+// instead of two: 14o14e 5.50 -> 5.29 ms).
 template <typename T>
-constexpr int col_threads() { return sizeof(T) == 4 ? 768 : 512; }
+constexpr int col_threads() { return 768; }
 
 template <typename T, int K>
 struct ColShape {
@@ -395,10 +396,11 @@ struct ColSplit {
   static constexpr int64_t lds = vf_bytes + col_bytes + s_bytes + brow_bytes;
 };
 
-// FP32: three waves per SIMD with a shorter load lookahead (fits the
-// registers of the single pass); FP64: two waves
+// Three waves per SIMD in both precisions; FP32 with a shorter load
+// lookahead (fits the registers of its single pass).  FP64 with three waves
+// instead of two: 16o16e 155 -> 140 ms.
 template <typename T>
-constexpr int split_threads() { return sizeof(T) == 4 ? 768 : 512; }
+constexpr int split_threads() { return 768; }
 
 template <typename T, int K>
 __global__ void __launch_bounds__(split_threads<T>()) sigma_column_split_kernel(
