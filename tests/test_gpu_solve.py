@@ -190,3 +190,34 @@ def test_separable_bodies_closed_form():
         q = synthetic.Problem(p.h[np.ix_(orbs, orbs)], p.eri[np.ix_(orbs, orbs, orbs, orbs)], [[0, 1]], [1], 1)
         corr += fci.solve_increment(q, (0,))["E"] - oifci.reference_energy(q)
     assert abs(res["total"] - (res["e_ref"] + corr)) < 1e-10
+
+
+ODD = [
+    ("1o", dict(n_bodies=3, orbs_per_body=1, nocc_per_body=1, order=3, seed=311)),
+    ("3o1e", dict(n_bodies=3, orbs_per_body=3, nocc_per_body=1, order=2, seed=312)),
+    ("3o2e", dict(n_bodies=2, orbs_per_body=3, nocc_per_body=2, order=2, seed=313)),
+]
+
+
+@pytest.mark.parametrize("space", SPACES)
+@pytest.mark.parametrize("name,kw", ODD, ids=[n for n, _ in ODD])
+def test_solve_odd_shapes(name, kw, space):
+    """The on-chip solvers on odd orbital counts and fillings away from half
+    (1-orbital increments with no off-diagonal pair, 3o/6o increments with one
+    or two electrons per spin and body), FP64 and mixed, against the oracle's
+    exact increment energies."""
+    import torch
+    print(f"[solve] odd shapes {name} max_space {space}", flush=True)
+    p = synthetic.chain(**kw)
+    plan64, r64 = ifci.solve(p, r_tol=1e-9, max_iter=500, max_space=space)
+    plan32, r32 = ifci.solve(p, precision=ifci.MIXED, r_tol=3e-5, r_tol_inner=1e-5, max_iter=500,
+                             max_space=space)
+    torch.cuda.synchronize()
+    E64 = r64["E"].cpu().numpy()
+    E32 = r32["E"].cpu().numpy()
+    assert (r64["status"].cpu().numpy() == ifci.INC_DONE).all()
+    assert (r32["status"].cpu().numpy() == ifci.INC_DONE).all()
+    for i, inc in enumerate(plan64.increments()):
+        want = fci.solve_increment(p, inc.bodies)["E"]
+        assert abs(E64[i] - want) <= TOL64, (name, inc.bodies, E64[i] - want)
+        assert abs(E32[i] - want) <= 1e-6, (name, inc.bodies, E32[i] - want)
