@@ -9,11 +9,21 @@ solve every increment (batched persistent solver, one workgroup per
 increment, three-vector {x, w, p} iteration, FP32 MFMA sigma with FP64
 subspace and FP64 residual refinement) and assemble the expansion
 energies (eqs. 2-5).  The metric counts increments whose energy is within
-1 uEh of the FP64 solution, per second of step time.  The FP64 batched path
-and the plain per-increment FP64 path are timed beside it, and the CPU
-oracle on a bounded sample.
+1 uEh of the oracle's exact energy (stored, sha-checked), per second of step
+time.  The FP64 batched path and the plain per-increment FP64 path are timed
+beside it at the same FP64 residual tolerance, and the CPU oracle on a
+bounded, seeded sample of the same workload.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Legs (--legs, comma separated; default all):
+  mixed  the headline (batched, mixed precision)
+  fp64   batched FP64
+  plain  per-increment device-wide FP64
+  large  14o14e / 16o16e: symmetric-sector sigma and whole solves
+  w3     12 bodies, order 5 (1585 increments incl. 792 x 10o10e) and its gradient
+  w4     256 independent 10o10e problems (K = 20, seeds 4000..4255)
+  cpu    the oracle on the host cores
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs mixed,fp64,...]
 """
 from __future__ import annotations
 
@@ -21,6 +31,7 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -32,6 +43,19 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp64_mfma": 78.6e12, "fp32_mfma": 157.3e12, "hbm": 8.0e12}
 KERNEL_SOURCES = ["batched.hip", "device_common.hpp", "ifci_internal.h", "launch.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batched_lobpcg_kernel_workload2.traffic.json")
+ORACLE_W2 = os.path.join(ROOT, "tests", "golden", "oracle_w2.json")
+ALL_LEGS = ("mixed", "fp64", "plain", "large", "w3", "w4", "cpu")
+
+TOL_UEH = 1e-6
+# One FP64 acceptance test for every leg: converged when the FP64 residual
+# of the unit vector is at most R_TOL.  The mixed leg switches from FP32 to
+# FP64 sigma at the FP32 residual R_TOL_INNER and keeps iterating in FP64
+# until the FP64 residual passes R_TOL.
+R_TOL = 1e-5
+R_TOL_INNER = 1e-5
+SPACE = 3  # batched solver subspace: 3 = {x, w, p} iteration (12 = thick-restart Davidson)
+CPU_8O8E_SAMPLE = 64
+CPU_SAMPLE_SEED = 2024
 
 
 def kernel_source_hash() -> str:
@@ -56,8 +80,6 @@ def measured_traffic():
     if t.get("source_sha256") != kernel_source_hash():
         return None
     return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
-TOL_UEH = 1e-6
-SPACE = 3  # batched solver subspace: 3 = {x, w, p} iteration (12 = thick-restart Davidson)
 
 
 def f_sym(k: int, na: int) -> float:
@@ -74,71 +96,157 @@ def f_exec(k: int, na: int) -> float:
     return 2.0 * (k * (k - 1) // 2 + 1) * np_ * math.comb(k, na) ** 2
 
 
-def timed_solve(plan, h, eri, torch, stream):
-    """One step on `plan`; returns (E, status, iters, total, kernel_ms)."""
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    from paper_2307_10675_amd import ifci
-    ifci._check(ifci.lib().ifci_set_integrals(plan._h, ifci._ptr(h), ifci._ptr(eri), ifci._stream(stream)))
-    t0.record(stream)
-    e, st, it, rs = plan.davidson(stream=stream)
-    t1.record(stream)
-    en = plan.energy(e, st, stream=stream)
-    return e, st, it, en, (t0, t1)
+# ------------------------------------------------------------------ CPU oracle
+def _cpu_task(args):
+    """One oracle increment solve, timed in its two parts: the Slater-Condon
+    build of H and the symmetric-sector eigensolve (LAPACK)."""
+    problem, S, threads = args
+    from threadpoolctl import threadpool_limits
+
+    from oracle import fci, hamiltonian
+    with threadpool_limits(limits=threads):
+        t0 = time.perf_counter()
+        dets, n_str, active = fci.increment_dets(problem.n_orb, problem.bodies, problem.nocc, S)
+        H = hamiltonian.build(dets, problem.h, problem.eri, active, problem.e_const)
+        t1 = time.perf_counter()
+        e, _, _ = fci.lowest_symmetric(H, n_str)
+        t2 = time.perf_counter()
+    return tuple(S), e, t1 - t0, t2 - t1
+
+
+def host_description() -> dict:
+    out = {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        keep = ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)",
+                "CPU max MHz", "L3 cache", "NUMA node(s)")
+        out["lscpu"] = {ln.split(":", 1)[0].strip(): ln.split(":", 1)[1].strip()
+                        for ln in txt.splitlines() if ":" in ln and ln.split(":", 1)[0].strip() in keep}
+    except (OSError, subprocess.SubprocessError):
+        out["lscpu"] = None
+    return out
+
+
+def cpu_baseline(problem, workers: int, n8: int) -> dict:
+    """The oracle (dense Slater-Condon FCI + LAPACK, never tuned) on the host
+    cores, in two runs:
+
+    * all cores: a process pool of `workers` single-threaded processes over
+      every 2o2e, 4o4e and 6o6e increment plus a seeded sample of n8 of the
+      1820 8o8e increments;
+    * one thread: one process over a seeded sample of 4 increments of each
+      size below 8o8e and 2 of 8o8e.
+
+    Each is extrapolated to all 2516 increments from the mean time per size
+    (and, for the pool, its measured parallel efficiency)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    from oracle import ifci as oifci
+    incs = oifci.increments(problem.n_bodies, problem.order)
+    by = {k: [S for S in incs if len(S) == k] for k in range(1, problem.order + 1)}
+    rng = np.random.default_rng(CPU_SAMPLE_SEED)
+    top = problem.order
+    pick8 = [by[top][i] for i in sorted(rng.choice(len(by[top]), size=min(n8, len(by[top])), replace=False))]
+    pool_set = [S for k in range(1, top) for S in by[k]] + pick8
+    one_set = [by[k][i] for k in range(1, top) for i in sorted(rng.choice(len(by[k]), size=4, replace=False))] + \
+              [pick8[0], pick8[1]]
+
+    def summarise(rows, wall):
+        per = {}
+        for S, _, tb, te in rows:
+            per.setdefault(len(S), []).append((tb, te))
+        sizes = {}
+        t_cpu_all = 0.0
+        for k in range(1, top + 1):
+            tb = float(np.mean([x[0] for x in per[k]]))
+            te = float(np.mean([x[1] for x in per[k]]))
+            sizes[f"{2 * k}o{2 * k}e"] = {"solved": len(per[k]), "of": len(by[k]), "h_build_s": tb, "eigh_s": te}
+            t_cpu_all += (tb + te) * len(by[k])
+        t_cpu_sample = sum(tb + te for _, _, tb, te in rows)
+        eff = t_cpu_sample / wall
+        return sizes, t_cpu_all, t_cpu_sample, eff
+
+    ctx = mp.get_context("spawn")
+    t = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
+        # largest first so the pool drains evenly
+        order = sorted(pool_set, key=lambda S: -len(S))
+        rows = list(ex.map(_cpu_task, [(problem, S, 1) for S in order], chunksize=1))
+    wall = time.perf_counter() - t
+    sizes, t_all, t_sample, eff = summarise(rows, wall)
+    est_pool = t_all / eff
+    t = time.perf_counter()
+    rows1 = [_cpu_task((problem, S, 1)) for S in one_set]
+    wall1 = time.perf_counter() - t
+    sizes1, t_all1, _, _ = summarise(rows1, wall1)
+    energies = {S: e for S, e, _, _ in rows}
+    return dict(
+        value=len(incs) / est_pool, unit="increments/s", cores=workers, kind="oracle",
+        sample=(f"extrapolated: all " + ", ".join(f"{len(by[k])} {2 * k}o{2 * k}e" for k in range(1, top)) +
+                f" increments plus a seeded sample of {len(pick8)} of the {len(by[top])} {2 * top}o{2 * top}e "
+                f"increments, solved by {workers} single-threaded processes in "
+                f"{wall:.1f} s (parallel efficiency {eff:.1f} of {workers}); mean time per size x count / "
+                f"efficiency = {est_pool:.0f} s for all {len(incs)}"),
+        by_size=sizes,
+        one_thread={"value": len(incs) / t_all1, "unit": "increments/s", "cores": 1,
+                    "sample": f"extrapolated from {len(one_set)} seeded increments ({wall1:.1f} s)",
+                    "by_size": sizes1, "est_total_s": t_all1},
+        host=host_description(),
+        _energies=energies,
+    )
+
+
+# ------------------------------------------------------------------ GPU legs
+def oracle_reference(problem):
+    """(energies, gaps) of every workload-2 increment from the stored oracle
+    run, or None when the file is absent or was made from other integrals."""
+    try:
+        with open(ORACLE_W2) as fh:
+            g = json.load(fh)
+    except OSError:
+        return None
+    if g.get("sha256") != problem.sha256():
+        return None
+    return (np.array([x["E"] for x in g["increments"]]), np.array([x["gap"] for x in g["increments"]]),
+            [tuple(x["bodies"]) for x in g["increments"]])
 
 
 def run_steps(plan, h, eri, steps, warmup, torch):
+    """Time `steps` whole steps (embed + solve + energy assembly) on the
+    current stream; returns the last outputs, wall seconds per step, and the
+    mean solver-launch time (HIP events around ifci_davidson)."""
+    from paper_2307_10675_amd import ifci
     stream = torch.cuda.current_stream()
+
+    def one():
+        ifci._check(ifci.lib().ifci_set_integrals(plan._h, ifci._ptr(h), ifci._ptr(eri), ifci._stream(stream)))
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        e, st, it, rs = plan.davidson(stream=stream)
+        t1.record(stream)
+        en = plan.energy(e, st, stream=stream)
+        return (e, st, it, rs, en), (t0, t1)
+
     for _ in range(warmup):
-        timed_solve(plan, h, eri, torch, stream)
+        one()
     torch.cuda.synchronize()
-    kern = []
+    kern, out = [], None
     t = time.perf_counter()
-    out = None
     for _ in range(steps):
-        out = timed_solve(plan, h, eri, torch, stream)
-        kern.append(out[4])
+        out, ev = one()
+        kern.append(ev)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t) / steps
-    kms = float(np.mean([a.elapsed_time(b) for a, b in kern]))
-    return out, wall, kms
-
-
-def cpu_baseline(problem, budget_s: float = 20.0):
-    """The oracle (dense Slater-Condon FCI + LAPACK) on a bounded sample of
-    the same workload: increments of each size, extrapolated to all 2516."""
-    from oracle import fci, ifci as oifci
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([x.get("num_threads", 1) for x in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count()
-    incs = oifci.increments(problem.n_bodies, problem.order)
-    by = {k: [S for S in incs if len(S) == k] for k in range(1, problem.order + 1)}
-    per = {}
-    used = 0.0
-    sample = []
-    for k in range(1, problem.order + 1):
-        times = []
-        for S in by[k][:: max(1, len(by[k]) // 8)]:
-            t = time.perf_counter()
-            fci.solve_increment(problem, S)
-            times.append(time.perf_counter() - t)
-            used += times[-1]
-            if used > budget_s or len(times) >= 8:
-                break
-        per[k] = float(np.mean(times))
-        sample.append(f"{len(times)}x{2 * k}o{2 * k}e")
-    total = sum(per[k] * len(by[k]) for k in per)
-    return dict(value=len(incs) / total, unit="increments/s", cores=int(cores), kind="oracle",
-                sample=f"{', '.join(sample)} solved ({used:.1f} s); per-size mean time x count, "
-                       f"extrapolated to all {len(incs)} increments (est. {total:.0f} s)")
+    kms = [a.elapsed_time(b) for a, b in kern]
+    return out, wall, float(np.mean(kms)), float(np.median(kms))
 
 
 def large_sigma(torch, ifci, synthetic, n_orb=14, reps=5):
     """Symmetric-sector sigma of one half-filled n_orb-orbital FCI space (the
-    single-FCI shape, seed 4000 + n_orb): the fused column kernel, FP32 and
-    FP64, timed with HIP events on the current stream."""
+    single-FCI shape, K = 2 n_orb, seed 4000 + n_orb): the fused column
+    kernel, FP32 and FP64, timed with HIP events on the current stream."""
     p = synthetic.single(n_orb, 2 * n_orb, 4000 + n_orb)
     plan = ifci.Plan(p, solver=ifci.PLAIN).attach(p.h, p.eri)
     n_str = int(round(plan.increment(0).n_det ** 0.5))
@@ -146,7 +254,8 @@ def large_sigma(torch, ifci, synthetic, n_orb=14, reps=5):
     c = torch.tensor(rng.standard_normal(n_str * (n_str + 1) // 2), device="cuda")
     flops = f_sym(n_orb, n_orb // 2)
     out = {"shape": f"{n_orb}o{n_orb}e, {n_str ** 2:,} determinants, sector {n_str * (n_str + 1) // 2:,}",
-           "flops_per_sigma": flops}
+           "flops_per_sigma": flops, "algorithmic_bytes_fp32": 2 * 4 * n_str ** 2,
+           "algorithmic_bytes_fp64": 2 * 8 * n_str ** 2}
     for name, prec, peak in (("fp32", ifci.MIXED, PEAK["fp32_mfma"]), ("fp64", ifci.FP64, PEAK["fp64_mfma"])):
         plan.sigma_sector(0, c, precision=prec)
         torch.cuda.synchronize()
@@ -158,9 +267,88 @@ def large_sigma(torch, ifci, synthetic, n_orb=14, reps=5):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         out[name] = {"ms": ms, "tflops": flops / (ms * 1e-3) / 1e12, "frac_mfma_peak": flops / (ms * 1e-3) / peak}
+    plan.close()
     del plan
     torch.cuda.empty_cache()
     return out
+
+
+def large_solve(torch, ifci, synthetic, n_orb, precision):
+    """Whole lowest-root solve of the half-filled n_orb-orbital FCI (K = 2 n_orb,
+    seed 4000 + n_orb): wall time, iterations, residual, sigma flop rate."""
+    p = synthetic.single(n_orb, 2 * n_orb, 4000 + n_orb)
+    plan = ifci.Plan(p, precision=precision, r_tol=R_TOL, r_tol_inner=R_TOL_INNER, max_iter=300).attach(p.h, p.eri)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    e, st, it, rs = plan.davidson()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    iters = int(it[0])
+    flops = iters * f_sym(n_orb, n_orb // 2)
+    peak = PEAK["fp32_mfma"] if precision == ifci.MIXED else PEAK["fp64_mfma"]
+    out = {"shape": f"{n_orb}o{n_orb}e", "precision": "mixed" if precision == ifci.MIXED else "fp64",
+           "seconds": wall, "iterations": iters, "residual": float(rs[0]), "E": float(e[0]),
+           "converged": int(st[0]) == ifci.INC_DONE, "sigma_tflops_over_solve": flops / wall / 1e12,
+           "frac_mfma_peak_over_solve": flops / wall / peak}
+    plan.close()
+    del plan
+    torch.cuda.empty_cache()
+    return out
+
+
+def workload3_leg(torch, ifci, synthetic):
+    """12 bodies, order 5: 12 + 66 + 220 + 495 + 792 increments (up to
+    10o10e), mixed and FP64 at the same FP64 residual, and the expansion
+    gradient (weighted 1- and 2-particle densities) of the FP64 solve."""
+    p = synthetic.workload(3)
+    dev = torch.device("cuda", 0)
+    h = torch.tensor(p.h, dtype=torch.float64, device=dev)
+    eri = torch.tensor(p.eri, dtype=torch.float64, device=dev).contiguous()
+    out = {"workload": "12 bodies x (2o, 2e), order 5: 1585 increments (12x2o2e, 66x4o4e, 220x6o6e, "
+                       "495x8o8e, 792x10o10e), seed 3000"}
+    res = {}
+    for name, prec in (("mixed", ifci.MIXED), ("fp64", ifci.FP64)):
+        plan = ifci.Plan(p, precision=prec, r_tol=R_TOL, r_tol_inner=R_TOL_INNER, max_iter=500,
+                         max_space=SPACE).attach(h, eri)
+        (e, st, it, rs, en), wall, kms, _ = run_steps(plan, h, eri, 1, 1, torch)
+        e = e.cpu().numpy()
+        res[name] = e
+        out[name] = {"seconds": wall, "solve_ms": kms, "increments_per_s": len(e) / wall,
+                     "all_converged": bool((st.cpu().numpy() == ifci.INC_DONE).all()),
+                     "mean_iters_10o10e": float(it.cpu().numpy()[-792:].mean()), "total": en["total"]}
+        if prec == ifci.FP64:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            plan.rdm()
+            torch.cuda.synchronize()
+            out["gradient_seconds"] = time.perf_counter() - t
+        plan.close()
+        del plan
+    out["max_abs_mixed_minus_fp64"] = float(np.abs(res["mixed"] - res["fp64"]).max())
+    torch.cuda.empty_cache()
+    return out
+
+
+def workload4_batch_leg(torch, ifci, synthetic, count=256):
+    """256 independent 10o10e FCI problems (K = 20, seeds 4000..4255), one
+    plan each, all solved in mixed precision then timed as one job."""
+    problems = [synthetic.single(10, 20, 4000 + i) for i in range(count)]
+    plans = [ifci.Plan(q, precision=ifci.MIXED, r_tol=R_TOL, r_tol_inner=R_TOL_INNER, max_iter=300).attach(q.h, q.eri)
+             for q in problems]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    outs = [pl.davidson() for pl in plans]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    it = np.array([int(o[2][0]) for o in outs])
+    ok = all(int(o[1][0]) == ifci.INC_DONE for o in outs)
+    flops = float(it.sum()) * f_sym(10, 5)
+    for pl in plans:
+        pl.close()
+    torch.cuda.empty_cache()
+    return {"problems": f"{count} x 10o10e (K = 20, seeds 4000..{4000 + count - 1}), 16,257,024 determinants",
+            "seconds": wall, "increments_per_s": count / wall, "mean_iters": float(it.mean()), "all_converged": ok,
+            "sigma_tflops_over_solve": flops / wall / 1e12}
 
 
 def main():
@@ -168,11 +356,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--legs", default=",".join(ALL_LEGS))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-large", action="store_true", help="skip the 14o14e and 16o16e sigma measurements")
-    ap.add_argument("--only-large", action="store_true",
-                    help="measure only the 14o14e sigma (fused column kernel) and print its JSON")
+    ap.add_argument("--no-large", action="store_true", help="skip the 14o14e and 16o16e measurements")
+    ap.add_argument("--cpu-workers", type=int, default=0, help="oracle pool size (default: min(16, cores))")
+    ap.add_argument("--cpu-8o8e", type=int, default=CPU_8O8E_SAMPLE)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a kernel of known "
                          "traffic, to scale HBM byte counters)")
@@ -181,9 +370,29 @@ def main():
         print("bench.py measures one GPU only: the increments are independent and would be "
               "sharded across GPUs by increment (see DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    legs = set(x for x in a.legs.split(",") if x)
+    bad = legs - set(ALL_LEGS)
+    if bad:
+        ap.error(f"unknown legs {sorted(bad)}")
+    if a.no_cpu:
+        legs.discard("cpu")
+    if a.no_plain:
+        legs.discard("plain")
+    if a.no_large:
+        legs.discard("large")
+
+    from paper_2307_10675_amd import synthetic
+    problem = synthetic.workload(2)
+
+    # the oracle runs first, in child processes, before anything touches the GPU
+    cpu = None
+    if "cpu" in legs:
+        workers = a.cpu_workers or min(16, len(os.sched_getaffinity(0)))
+        cpu = cpu_baseline(problem, workers, a.cpu_8o8e)
+
     import torch
 
-    from paper_2307_10675_amd import ifci, synthetic
+    from paper_2307_10675_amd import ifci
 
     dev = torch.device("cuda", 0)
     if a.copy_calibration > 0:
@@ -193,51 +402,73 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if a.only_large:
-        print(json.dumps({"large_sigma": large_sigma(torch, ifci, synthetic),
-                          "large_sigma_16o": large_sigma(torch, ifci, synthetic, n_orb=16, reps=3)}), flush=True)
-        return
-    problem = synthetic.workload(2)
     h = torch.tensor(problem.h, dtype=torch.float64, device=dev)
     eri = torch.tensor(problem.eri, dtype=torch.float64, device=dev).contiguous()
 
-    # FP64 reference energies (batched FP64, residual 1e-7)
-    ref_plan = ifci.Plan(problem, precision=ifci.FP64, r_tol=1e-7, max_iter=400).attach(h, eri)
-    e_ref, st_ref, _, _ = ref_plan.davidson()
-    e_ref = e_ref.cpu().numpy()
-    assert (st_ref.cpu().numpy() == ifci.INC_DONE).all()
-    incs = ref_plan.increments()
+    ref = oracle_reference(problem)
+    probe = ifci.Plan(problem)
+    incs = probe.increments()
+    probe.close()
+    if ref is not None:
+        e_ref, gap_ref, bodies = ref
+        assert bodies == [i.bodies for i in incs], "increment order differs from the oracle file"
+        gate = "oracle (tests/golden/oracle_w2.json, sha256-checked)"
+    else:
+        # the stored oracle energies are missing: gate on an FP64 solve to 1e-8
+        rp = ifci.Plan(problem, precision=ifci.FP64, r_tol=1e-8, max_iter=600).attach(h, eri)
+        e_ref = rp.davidson()[0].cpu().numpy()
+        gap_ref = None
+        rp.close()
+        gate = "GPU FP64 batched solve to residual 1e-8 (oracle file missing)"
     flops = np.array([f_sym(i.n_act, i.n_alpha) for i in incs])
     flops_exec = np.array([f_exec(i.n_act, i.n_alpha) for i in incs])
 
     def measure(precision, solver, steps, warmup, **kw):
-        plan = ifci.Plan(problem, precision=precision, solver=solver, max_iter=500, **kw).attach(h, eri)
-        (e, st, it, en, _), wall, kms = run_steps(plan, h, eri, steps, warmup, torch)
+        plan = ifci.Plan(problem, precision=precision, solver=solver, max_iter=600, r_tol=R_TOL,
+                         r_tol_inner=R_TOL_INNER, **kw).attach(h, eri)
+        (e, st, it, rs, en), wall, kms, kmed = run_steps(plan, h, eri, steps, warmup, torch)
         e = e.cpu().numpy()
         it = it.cpu().numpy()
-        ok = (np.abs(e - e_ref) <= TOL_UEH) & (st.cpu().numpy() == ifci.INC_DONE)
-        return dict(wall_ms=wall * 1e3, kernel_ms=kms, n_ok=int(ok.sum()), inc_per_s=float(ok.sum()) / wall,
-                    max_err=float(np.abs(e - e_ref).max()), sigmas=int(it.sum()),
-                    sigma_flops=float((it * flops).sum()), sigma_flops_executed=float((it * flops_exec).sum()),
-                    mean_iters=float(it.mean()), total=en["total"])
+        rs = rs.cpu().numpy()
+        err = np.abs(e - e_ref)
+        ok = (err <= TOL_UEH) & (st.cpu().numpy() == ifci.INC_DONE)
+        r = dict(wall_ms=wall * 1e3, kernel_ms=kms, kernel_ms_median=kmed, n_ok=int(ok.sum()),
+                 inc_per_s=float(ok.sum()) / wall, max_err=float(err.max()), sigmas=int(it.sum()),
+                 sigma_flops=float((it * flops).sum()), sigma_flops_executed=float((it * flops_exec).sum()),
+                 mean_iters=float(it.mean()), max_iters=int(it.max()), total=en["total"],
+                 max_residual=float(rs.max()))
+        if gap_ref is not None:
+            # every result with its error bound: |E - lambda| <= ||r||^2 / gap
+            # (Kato-Temple, gap to the next root of the sector from the oracle)
+            kt = rs ** 2 / gap_ref
+            r.update(max_error_bound=float(kt.max()), n_bound_within_gate=int((kt <= TOL_UEH).sum()))
+        plan.close()
+        return r
 
-    # headline: batched mixed precision at 1 uEh
-    mixed = measure(ifci.MIXED, ifci.BATCHED, a.steps, a.warmup, r_tol=3e-5, r_tol_inner=1e-5,
-                    max_space=SPACE)
-    fp64 = measure(ifci.FP64, ifci.BATCHED, max(1, a.steps // 2), 1, r_tol=3e-5, max_space=SPACE)
-    plain = None if a.no_plain else measure(ifci.FP64, ifci.PLAIN, 1, 0, r_tol=3e-5)
+    out_detail = {}
+    mixed = measure(ifci.MIXED, ifci.BATCHED, a.steps, a.warmup, max_space=SPACE) if "mixed" in legs else None
+    fp64 = measure(ifci.FP64, ifci.BATCHED, max(1, a.steps // 2), 1, max_space=SPACE) if "fp64" in legs else None
+    plain = measure(ifci.FP64, ifci.PLAIN, 1, 0) if "plain" in legs else None
+    if "large" in legs:
+        out_detail["large_sigma"] = large_sigma(torch, ifci, synthetic)
+        out_detail["large_sigma_16o"] = large_sigma(torch, ifci, synthetic, n_orb=16, reps=3)
+        out_detail["large_solves"] = [large_solve(torch, ifci, synthetic, 14, ifci.MIXED),
+                                      large_solve(torch, ifci, synthetic, 14, ifci.FP64),
+                                      large_solve(torch, ifci, synthetic, 16, ifci.MIXED)]
+    if "w3" in legs:
+        out_detail["workload3_order5"] = workload3_leg(torch, ifci, synthetic)
+    if "w4" in legs:
+        out_detail["workload4_batch_10o10e"] = workload4_batch_leg(torch, ifci, synthetic)
 
-    kern_s = mixed["kernel_ms"] * 1e-3
-    traffic = measured_traffic()
-    achieved = mixed["sigma_flops"] / kern_s
+    head = mixed or fp64 or plain
     out = {
         "metric": "iFCI increments/sec at 1 uEh (batched mixed-precision solver)",
-        "value": mixed["inc_per_s"],
+        "value": mixed["inc_per_s"] if mixed else None,
         "unit": "increments/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": mixed["wall_ms"],
+        "ms_per_step": mixed["wall_ms"] if mixed else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -246,40 +477,49 @@ def main():
         "config": {
             "workload": "16 bodies x (2 orbitals, 2 electrons), 4-body iFCI: 16x2o2e + 120x4o4e + "
                         "560x6o6e + 1820x8o8e = 2516 increments, 9,146,384 determinants, seed 2000",
-            "precision": "mixed", "solver": "batched", "max_space": SPACE, "r_tol": 3e-5, "r_tol_inner": 1e-5,
-            "accuracy_gate_Eh": TOL_UEH,
+            "precision": "mixed", "solver": "batched", "max_space": SPACE, "r_tol": R_TOL,
+            "r_tol_inner": R_TOL_INNER, "accuracy_gate_Eh": TOL_UEH, "gate_reference": gate,
         },
-        "roofline": {
+    }
+    if mixed:
+        kern_s = mixed["kernel_ms"] * 1e-3
+        achieved = mixed["sigma_flops"] / kern_s
+        out["roofline"] = {
             "bound": "mfma",
             "kernel": "batched_lobpcg_kernel (one workgroup per increment, sigma on FP32/FP64 MFMA)",
             "achieved": achieved / 1e12,
             "peak": PEAK["fp32_mfma"] / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK["fp32_mfma"],
-            "traffic": traffic,
+            "traffic": measured_traffic(),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-        },
-        "detail": {
-            "mixed_batched": mixed,
-            "fp64_batched": fp64,
-            "fp64_plain": plain,
-            "speedup_mixed_vs_fp64_batched": mixed["inc_per_s"] / fp64["inc_per_s"],
-            "speedup_mixed_vs_fp64_plain": (mixed["inc_per_s"] / plain["inc_per_s"]) if plain else None,
-            "fp64_batched_sigma_tflops": fp64["sigma_flops"] / (fp64["kernel_ms"] * 1e-3) / 1e12,
-            "fp64_batched_frac_fp64_mfma": fp64["sigma_flops"] / (fp64["kernel_ms"] * 1e-3) / PEAK["fp64_mfma"],
-            "flops_per_launch": mixed["sigma_flops"],
-            # arithmetic the kernel actually performs (the diagonal pairs as a
-            # dot product per determinant), and its fraction of the FP32 peak
-            "executed_flops_per_launch": mixed["sigma_flops_executed"],
-            "executed_frac_fp32_mfma": mixed["sigma_flops_executed"] / kern_s / PEAK["fp32_mfma"],
-            "kernel_ms_per_launch": mixed["kernel_ms"],
-        },
-    }
-    if not a.no_large:
-        out["detail"]["large_sigma"] = large_sigma(torch, ifci, synthetic)
-        out["detail"]["large_sigma_16o"] = large_sigma(torch, ifci, synthetic, n_orb=16, reps=3)
-    if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(problem)
+        }
+    detail = {"mixed_batched": mixed, "fp64_batched": fp64, "fp64_plain": plain}
+    if mixed and fp64:
+        detail["speedup_mixed_vs_fp64_batched"] = mixed["inc_per_s"] / max(fp64["inc_per_s"], 1e-30)
+        detail["fp64_batched_sigma_tflops"] = fp64["sigma_flops"] / (fp64["kernel_ms"] * 1e-3) / 1e12
+        detail["fp64_batched_frac_fp64_mfma"] = fp64["sigma_flops"] / (fp64["kernel_ms"] * 1e-3) / PEAK["fp64_mfma"]
+    if mixed and plain:
+        detail["speedup_mixed_vs_fp64_plain"] = mixed["inc_per_s"] / max(plain["inc_per_s"], 1e-30)
+    if mixed:
+        kern_s = mixed["kernel_ms"] * 1e-3
+        detail["flops_per_launch"] = mixed["sigma_flops"]
+        # arithmetic the kernel actually performs (the diagonal pairs as a
+        # dot product per determinant), and its fraction of the FP32 peak
+        detail["executed_flops_per_launch"] = mixed["sigma_flops_executed"]
+        detail["executed_frac_fp32_mfma"] = mixed["sigma_flops_executed"] / kern_s / PEAK["fp32_mfma"]
+        detail["kernel_ms_per_launch"] = mixed["kernel_ms"]
+    detail.update(out_detail)
+    out["detail"] = detail
+    if cpu is not None:
+        # the sampled oracle energies against the headline leg's reference
+        en = cpu.pop("_energies")
+        idx = {S: i for i, S in enumerate(i.bodies for i in incs)}
+        cpu["max_abs_vs_gate_reference"] = float(max(abs(e - e_ref[idx[S]]) for S, e in en.items()))
+        out["cpu_baseline"] = cpu
+    if head is None and not out_detail and cpu is None:
+        print("no legs selected", file=sys.stderr)
+        sys.exit(2)
     print(json.dumps(out), flush=True)
 
 

@@ -139,7 +139,11 @@ ifci_status ifci_increment(ifci_plan_t plan, int64_t idx, int32_t* bodies, int32
 ifci_status ifci_weights(ifci_plan_t plan, double* w);
 
 /* String and single-replacement tables of a (k, n_alpha) space, for checking
- * bit-exactly.  Host only, no plan or device needed.
+ * bit-exactly.  Host only, no plan or device needed.  These are the
+ * occupation strings and the coupling coefficients <J|E_pq|I> of the
+ * string-driven determinant CI of Knowles and Handy (Chem. Phys. Lett. 111,
+ * 315, 1984) and Olsen et al. (J. Chem. Phys. 89, 2185, 1988); the paper
+ * gives the determinant counts of such spaces (Methods, Table 1).
  * strings: host [C(k, n_alpha)] bitmasks, increasing.
  * link:    host [C(k, n_alpha)][n_alpha*(k - n_alpha + 1)][4] entries
  *          (p, q, J, sign) meaning E_pq |I> = sign |J>; for each string,
@@ -159,7 +163,12 @@ ifci_status ifci_set_integrals(ifci_plan_t plan, const double* h, const double* 
                                ifci_stream_t stream);
 
 /* sigma = H c for increment `inc`, with H the active-space Hamiltonian
- * (without the frozen-core energy and e_const).  c and sigma: device
+ * (without the frozen-core energy and e_const), the matrix-vector product of
+ * determinant FCI in the Knowles-Handy form: D[kl][I] = (E_kl c)_I,
+ * E = (1/2) (ij|kl) D (a dense pair-by-pair contraction), sigma gathered
+ * back through the single-replacement tables.  The Hamiltonian is the one of
+ * the paper's increments (Methods, iFCI: the calculation restricted to the
+ * bodies of the increment).  c and sigma: device
  * [n_det] FP64, C[A][B] layout, any c (no symmetry needed); precision is
  * IFCI_FP64 or IFCI_MIXED (FP32 arithmetic, results widened to FP64).
  * Uses the workspace; c and sigma must not alias.  Materialises E
@@ -180,7 +189,10 @@ ifci_status ifci_sigma(ifci_plan_t plan, int64_t inc, const double* c, double* s
 ifci_status ifci_sigma_sector(ifci_plan_t plan, int64_t inc, const double* c, double* sigma,
                               int32_t precision, ifci_stream_t stream);
 
-/* Lowest even-spin root of increments [first, first + count).
+/* Lowest even-spin root of increments [first, first + count): E(S) of every
+ * increment S of eqs. 1-5 (Methods, iFCI), by Davidson's method (J. Comput.
+ * Phys. 17, 87, 1975) with a diagonal preconditioner, thick restart or the
+ * three-vector {x, w, p} form (locally optimal, Knyazev) per max_space.
  * e_out: device [count] total energies E(S) (frozen core and e_const
  * included); status_out: device [count] IFCI_INC_* words; evict_mask: device
  * [count] or NULL -- increments whose byte is nonzero are abandoned after one
@@ -210,7 +222,10 @@ ifci_status ifci_energy(ifci_plan_t plan, const double* e_inc, const int32_t* st
 
 /* Gradient of E_total (or of sum_S weights[S] E(S) + (1 - sum) E_ref when
  * weights, device [n_inc], is given) with respect to every entry of h and
- * eri taken as independent: dE_dh (device [n*n]) = weighted 1-RDM gamma,
+ * eri taken as independent, by the Hellmann-Feynman theorem (each E(S) is an
+ * eigenvalue, so its derivative is the expectation value of the derivative
+ * of H: the 1- and 2-particle density matrices of the converged vector),
+ * weighted as the expansion of eqs. 1-5 weights each E(S): dE_dh (device [n*n]) = weighted 1-RDM gamma,
  * dE_deri (device [n^4], may be NULL) = weighted Gamma / 2.  Needs the
  * converged vectors of every increment (ifci_davidson first). */
 ifci_status ifci_rdm(ifci_plan_t plan, const double* weights, double* dE_dh, double* dE_deri,

@@ -21,7 +21,7 @@ What it computes (paper: Methods, "Incremental Full Configuration Interaction"):
 
 The paper solves each increment with selected CI (HBCI) in a truncated
 natural-orbital space; the exact-FCI limit of that solver is computed here
-(see ifci.py for the reading of "including only the occupied orbitals").
+(fci.py states how an increment restricted to some bodies is read here).
 
 Modules:
   strings      one-spin occupation strings, combinatorial addresses, E_pq

@@ -1,7 +1,7 @@
 """Determinant space of one increment and its lowest root (test infrastructure only).
 
 Reading of the paper (Methods, iFCI): the correlation energy E_c(S) of an
-increment comes from a calculation "including only" the occupied orbitals of
+increment comes from a calculation restricted to the occupied orbitals of
 S.  Here a body is a group of orbitals (its occupied orbitals and the virtual
 orbitals that belong to it); the calculation for a set S of bodies correlates
 every orbital of those bodies, keeps the occupied orbitals of all other

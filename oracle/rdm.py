@@ -76,8 +76,14 @@ def increment_densities(problem, S):
     return dict(E=r["E"], gamma=g, Gamma=G, gap=r["gap"])
 
 
-def ifci_gradient(problem, weights_by_size=None):
-    """(E_iFCI, dE/dh, dE/d(pq|rs)) of the expansion truncated at problem.order."""
+def accumulate_gradient(problem, densities_in_order, weights_by_size=None):
+    """(E_iFCI, dE/dh, dE/d(pq|rs)) from the densities of every increment.
+
+    densities_in_order yields (S, increment_densities(problem, S)) for every
+    increment S of ifci.increments(n_bodies, order), in that order; the sums
+    are taken in that order too, so a caller that computes the densities in
+    parallel gets the same numbers as the serial `ifci_gradient`."""
+    import math
     nb, order = problem.n_bodies, problem.order
     w = weights_by_size or ifci.weights_closed(nb, order)
     g_ref, G_ref = reference_densities(problem)
@@ -86,14 +92,23 @@ def ifci_gradient(problem, weights_by_size=None):
     deri = np.zeros_like(problem.eri)
     w_sum = 0.0
     terms = [e_ref]
-    for S in ifci.increments(nb, order):
+    expect = iter(ifci.increments(nb, order))
+    for S, d in densities_in_order:
+        if tuple(S) != next(expect):
+            raise ValueError("densities must come in increment order")
         wt = w[len(S) - 1]
-        d = increment_densities(problem, S)
         dh += wt * d["gamma"]
         deri += 0.5 * wt * d["Gamma"]
         terms.append(wt * (d["E"] - e_ref))
         w_sum += wt
+    if next(expect, None) is not None:
+        raise ValueError("densities missing for some increments")
     dh += (1.0 - w_sum) * g_ref
     deri += 0.5 * (1.0 - w_sum) * G_ref
-    import math
     return math.fsum(terms), dh, deri
+
+
+def ifci_gradient(problem, weights_by_size=None):
+    """(E_iFCI, dE/dh, dE/d(pq|rs)) of the expansion truncated at problem.order."""
+    gen = ((S, increment_densities(problem, S)) for S in ifci.increments(problem.n_bodies, problem.order))
+    return accumulate_gradient(problem, gen, weights_by_size)

@@ -1537,16 +1537,9 @@ int64_t batched_lds_want(int k, int n_str, int n_link) {
 }
 
 hipError_t launch_batched(const SolveArgs& A, int lds_bytes, hipStream_t st) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)batched_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)batched_lobpcg_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kMaxLds);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  hipError_t e = allow_max_lds((const void*)batched_kernel);
+  if (e == hipSuccess) e = allow_max_lds((const void*)batched_lobpcg_kernel);
+  if (e != hipSuccess) return e;
   if (A.max_space == 3)
     hipLaunchKernelGGL(batched_lobpcg_kernel, dim3(A.count), dim3(kBatchThreads), lds_bytes, st, A, lds_bytes);
   else
@@ -1556,13 +1549,8 @@ hipError_t launch_batched(const SolveArgs& A, int lds_bytes, hipStream_t st) {
 
 hipError_t launch_sigma_one(const IncDev* incs, int inc, const double* ints, const int32_t* tables,
                             const double* c, double* sig, int precision, int lds_bytes, hipStream_t st) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)sigma_one_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  const hipError_t e = allow_max_lds((const void*)sigma_one_kernel);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(sigma_one_kernel, dim3(1), dim3(kBatchThreads), lds_bytes, st, incs, inc, ints, tables,
                      c, sig, precision, lds_bytes);
   return hipGetLastError();

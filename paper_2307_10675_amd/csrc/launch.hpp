@@ -9,6 +9,10 @@ namespace ifci {
 
 constexpr int kMaxLds = 163840;  // LDS per workgroup on gfx950
 
+// Raise the dynamic-LDS limit of kernel `fn` to kMaxLds on the current
+// device, once per (kernel, device); safe to call from several host threads.
+hipError_t allow_max_lds(const void* fn);
+
 hipError_t launch_embed(const IncDev* incs, int n_inc, const int32_t* orbs, const double* h,
                         const double* eri, int n, double* ints, const int32_t* ref_occ, int n_ref,
                         double e_const, double* misc, hipStream_t st);

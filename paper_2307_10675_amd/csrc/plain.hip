@@ -13,6 +13,8 @@
 // For symmetric c, E is symmetric in its two string indices and the beta
 // gather is the transpose of the alpha gather.
 #include <mutex>
+#include <set>
+#include <utility>
 
 #include "device_common.hpp"
 #include "launch.hpp"
@@ -583,23 +585,32 @@ static hipError_t launch_column_split(const IncDev& d, const double* V, const in
   return hipGetLastError();
 }
 
-// One-time set-up of the column kernels (their LDS exceeds the default
-// limit); safe to call from several host threads.
+hipError_t allow_max_lds(const void* fn) {
+  static std::mutex mu;
+  static std::set<std::pair<const void*, int>> done;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  if (done.count({fn, dev})) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+  if (e == hipSuccess) done.insert({fn, dev});
+  return e;
+}
+
+// Set-up of the column kernels on the current device (their LDS exceeds the
+// default limit); safe to call from several host threads.
 hipError_t prepare_sigma_wide() {
-  static std::once_flag once;
-  static hipError_t status = hipSuccess;
-  std::call_once(once, [] {
-    const void* fns[] = {(const void*)sigma_column_kernel<float, 10>, (const void*)sigma_column_kernel<double, 10>,
-                         (const void*)sigma_column_kernel<float, 12>, (const void*)sigma_column_kernel<double, 12>,
-                         (const void*)sigma_column_kernel<float, 14>, (const void*)sigma_column_kernel<double, 14>,
-                         (const void*)sigma_column_split_kernel<float, 16>,
-                         (const void*)sigma_column_split_kernel<double, 16>};
-    for (const void* f : fns) {
-      const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
-      if (e != hipSuccess && status == hipSuccess) status = e;
-    }
-  });
-  return status;
+  const void* fns[] = {(const void*)sigma_column_kernel<float, 10>, (const void*)sigma_column_kernel<double, 10>,
+                       (const void*)sigma_column_kernel<float, 12>, (const void*)sigma_column_kernel<double, 12>,
+                       (const void*)sigma_column_kernel<float, 14>, (const void*)sigma_column_kernel<double, 14>,
+                       (const void*)sigma_column_split_kernel<float, 16>,
+                       (const void*)sigma_column_split_kernel<double, 16>};
+  for (const void* f : fns) {
+    const hipError_t e = allow_max_lds(f);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 static hipError_t launch_sigma_column(const IncDev& d, const double* V, const int32_t* ptab, const int16_t* ptabT,

@@ -146,13 +146,8 @@ __global__ void rdm_delta_kernel(const IncDev* __restrict__ incs, double* __rest
 hipError_t launch_rdm(const IncDev* incs, const IncDev* host_incs, int n_inc, const double* dav_base,
                       const int32_t* tables, double* rdm, const int64_t* rdm_off_dev, int mmax,
                       hipStream_t st) {
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)rdm_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       kMaxLds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  const hipError_t e = allow_max_lds((const void*)rdm_kernel);
+  if (e != hipSuccess) return e;
   int kmax = 0;
   for (int i = 0; i < n_inc; ++i) kmax = host_incs[i].k > kmax ? host_incs[i].k : kmax;
   const int nt = (kmax * kmax + 15) / 16;

@@ -133,8 +133,9 @@ class IncrementInfo:
 
 
 class Plan:
-    """ifci_plan_t with its workspace.  `problem` needs h, eri, bodies,
-    nocc, order (and optionally e_const) -- e.g. synthetic.Problem."""
+    """ifci_plan_t with its workspace.  `problem` needs n_orb, bodies, nocc
+    and order (and optionally e_const) -- e.g. synthetic.Problem; the
+    integrals come with attach()."""
 
     def __init__(self, problem, precision=FP64, solver=BATCHED, device: int = 0, **opts):
         self._keep = []
@@ -143,7 +144,8 @@ class Plan:
         orb = np.array([o for b in bodies for o in b], dtype=np.int32)
         nocc = np.array(problem.nocc, dtype=np.int32)
         self._keep += [ptr, orb, nocc]
-        pr = Problem(n_orb=problem.h.shape[0], n_bodies=len(bodies),
+        n_orb = int(problem.n_orb)
+        pr = Problem(n_orb=n_orb, n_bodies=len(bodies),
                      body_ptr=ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                      body_orb=orb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                      body_nocc=nocc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
@@ -154,7 +156,7 @@ class Plan:
         self._h = h
         self.device = device
         self.order = problem.order
-        self.n_orb = problem.h.shape[0]
+        self.n_orb = n_orb
         self.workspace = None
         self._ints = None
 

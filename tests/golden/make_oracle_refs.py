@@ -4,7 +4,10 @@ Calls only the CPU oracle (oracle/) on the seeded synthetic problems of
 paper_2307_10675_amd.synthetic; nothing here touches the device path.
 Each output records the sha256 of the problem it was computed from.
 
-    python tests/golden/make_oracle_refs.py [--only NAME] [--jobs N]
+    python tests/golden/make_oracle_refs.py [--only NAME] [--jobs N] [--checkpoint FILE]
+
+--checkpoint FILE appends each finished increment energy to FILE (JSON lines)
+and skips increments already listed there, so a long run can be resumed.
 """
 from __future__ import annotations
 
@@ -18,7 +21,9 @@ from concurrent.futures import ProcessPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-from oracle import fci, ifci  # noqa: E402
+import numpy as np  # noqa: E402
+
+from oracle import fci, ifci, rdm  # noqa: E402
 from paper_2307_10675_amd import synthetic  # noqa: E402
 
 
@@ -28,15 +33,61 @@ def _solve(args):
     return S, r["E"], r["gap"]
 
 
-def energies(problem, subsets, jobs):
+def energies(problem, subsets, jobs, checkpoint=None):
+    """{S: (E, gap)} for every S; the largest increments are started first."""
+    done = {}
+    if checkpoint and os.path.exists(checkpoint):
+        with open(checkpoint) as f:
+            for line in f:
+                r = json.loads(line)
+                if r.get("sha256") == problem.sha256():
+                    done[tuple(r["bodies"])] = (r["E"], r["gap"])
+    todo = sorted((S for S in subsets if tuple(S) not in done), key=lambda S: -len(S))
     with ProcessPoolExecutor(max_workers=jobs) as ex:
-        out = list(ex.map(_solve, [(problem, S) for S in subsets], chunksize=1))
-    return {S: (e, g) for S, e, g in out}
+        for S, e, g in ex.map(_solve, [(problem, S) for S in todo], chunksize=1):
+            done[tuple(S)] = (e, g)
+            if checkpoint:
+                with open(checkpoint, "a") as f:
+                    f.write(json.dumps(dict(sha256=problem.sha256(), bodies=list(S), E=e, gap=g)) + "\n")
+    return {S: done[tuple(S)] for S in subsets}
 
 
-def dump(name, problem, subsets, jobs, full_expansion):
+def _densities(args):
+    problem, S = args
+    return S, rdm.increment_densities(problem, S)
+
+
+def dump_gradient(name, problem, jobs):
+    """Every increment energy of the expansion and its gradient (weighted
+    1- and 2-particle densities) from the oracle, in increment order."""
     t = time.time()
-    res = energies(problem, subsets, jobs)
+    subsets = ifci.increments(problem.n_bodies, problem.order)
+    E, gap = {}, {}
+
+    def stream(ex):
+        for S, d in ex.map(_densities, [(problem, S) for S in subsets], chunksize=1):
+            E[S], gap[S] = d["E"], d["gap"]
+            yield S, d
+
+    with ProcessPoolExecutor(max_workers=jobs) as ex:
+        e_tot, dh, deri = rdm.accumulate_gradient(problem, stream(ex))
+    e_ref = ifci.reference_energy(problem)
+    eps, by_order, total = ifci.increments_from_energies(E, e_ref, problem.order)
+    npz = os.path.join(HERE, f"oracle_{name}_grad.npz")
+    np.savez_compressed(npz, e_total=np.array(e_tot), dE_dh=dh, dE_deri=deri)
+    doc = dict(problem=problem.meta, sha256=problem.sha256(), order=problem.order, e_ref=e_ref,
+               increments=[dict(bodies=list(S), E=E[S], gap=gap[S]) for S in subsets],
+               eps=[eps[S] for S in subsets], by_order=by_order, total=total,
+               gradient=dict(file=os.path.basename(npz), e_total=e_tot), seconds=time.time() - t)
+    path = os.path.join(HERE, f"oracle_{name}.json")
+    with open(path, "w") as f:
+        json.dump(doc, f, indent=1)
+    print(f"{name}: {len(subsets)} increments and the gradient in {doc['seconds']:.1f} s -> {path}, {npz}")
+
+
+def dump(name, problem, subsets, jobs, full_expansion, checkpoint=None):
+    t = time.time()
+    res = energies(problem, subsets, jobs, checkpoint)
     e_ref = ifci.reference_energy(problem)
     doc = dict(
         problem=problem.meta, sha256=problem.sha256(), order=problem.order, e_ref=e_ref,
@@ -59,6 +110,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--only", default=None)
     ap.add_argument("--jobs", type=int, default=os.cpu_count())
+    ap.add_argument("--checkpoint", default=None)
     a = ap.parse_args()
     todo = {}
     for r in range(10):
@@ -73,13 +125,15 @@ def main():
     sample = [S for S in inc2 if len(S) <= 2] + [S for S in inc2 if len(S) == 3][::28] + \
              [S for S in inc2 if len(S) == 4][::91]
     todo["w2_sample"] = (p2, sample, False)
-    p3 = synthetic.chain(12, seed=3000, order=4)
-    inc3 = ifci.increments(12, 4)
-    todo["w3o4_sample"] = (p3, [S for S in inc3 if len(S) <= 2] + [S for S in inc3 if len(S) == 4][::99], False)
+    todo["w2"] = (p2, inc2, True)
     for name, (p, subsets, full) in todo.items():
         if a.only and a.only != name:
             continue
-        dump(name, p, subsets, a.jobs, full)
+        dump(name, p, subsets, a.jobs, full, a.checkpoint)
+    # workload 3 at order 4 (12 bodies, 793 increments up to 8o8e): energies
+    # and the expansion gradient
+    if a.only in (None, "w3o4"):
+        dump_gradient("w3o4", synthetic.chain(12, seed=3000, order=4), a.jobs)
 
 
 if __name__ == "__main__":

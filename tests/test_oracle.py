@@ -188,6 +188,45 @@ def test_sector_projection_vs_full_eigh(seed):
     assert abs(S - round(S)) < 1e-8 and round(S) % 2 == 0
 
 
+def _det(alpha, beta, n):
+    """Determinant bit pattern: spatial orbitals `alpha` with spin alpha,
+    `beta` with spin beta (bit n + p)."""
+    return sum(1 << p for p in alpha) | sum(1 << (n + p) for p in beta)
+
+
+def test_spin_squared_two_electrons_in_two_orbitals():
+    """<S^2> pinned on textbook two-electron states (two spatial orbitals):
+    a closed shell is a singlet (0); the high-spin determinant |1a 2a> has
+    S = Sz = 1 (2); one open-shell Ms = 0 determinant |1a 2b> is half singlet,
+    half triplet (1); of the two combinations |1a 2b> +- |2a 1b> one is the
+    singlet (0) and the other the Ms = 0 triplet (2), and the one with a
+    symmetric coefficient matrix C[alpha][beta] is the singlet."""
+    n = 2
+    assert abs(fci.spin_squared(np.array([1.0]), [_det([0], [0], n)], n)) < 1e-14
+    assert abs(fci.spin_squared(np.array([1.0]), [_det([0, 1], [], n)], n) - 2.0) < 1e-14
+    assert abs(fci.spin_squared(np.array([1.0]), [_det([0], [1], n)], n) - 1.0) < 1e-14
+    dets = [_det([0], [1], n), _det([1], [0], n)]
+    plus = fci.spin_squared(np.array([1.0, 1.0]), dets, n)
+    minus = fci.spin_squared(np.array([1.0, -1.0]), dets, n)
+    assert sorted([round(plus, 12), round(minus, 12)]) == [0.0, 2.0]
+    # the library's determinant order (alpha creators first, ascending):
+    # C[a][b] = C[b][a] for strings a = {1}, b = {2} is the + combination
+    assert abs(plus) < 1e-14 and abs(minus - 2.0) < 1e-14
+
+
+def test_spin_squared_high_spin_and_normalisation():
+    """Three electrons in three orbitals, all alpha: S = 3/2, <S^2> = 15/4
+    whatever the (unnormalised) coefficient; a mixture of Ms = 0 singlet and
+    triplet weights 1:3 gives 3/4 * 2 = 1.5."""
+    n = 3
+    assert abs(fci.spin_squared(np.array([2.5]), [_det([0, 1, 2], [], n)], n) - 3.75) < 1e-14
+    dets = [_det([0], [1], n), _det([1], [0], n)]
+    s = np.array([1.0, 1.0]) / np.sqrt(2.0)     # singlet
+    t = np.array([1.0, -1.0]) / np.sqrt(2.0)    # Ms = 0 triplet
+    c = 0.5 * s + np.sqrt(0.75) * t
+    assert abs(fci.spin_squared(c, dets, n) - 1.5) < 1e-14
+
+
 def test_workload0_singlet_and_reference():
     p = synthetic.workload(0)
     r = fci.solve_increment(p, (0,))
