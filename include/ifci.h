@@ -104,8 +104,15 @@ typedef struct {
                          2..16; in the batched solver 3 selects the
                          three-vector {x, w, p} iteration (locally
                          optimal, no restarts) */
-  uint32_t flags;     /* reserved, 0 */
+  uint32_t flags;     /* IFCI_FLAG_* bits */
 } ifci_options;
+
+/* ifci_davidson returns as soon as the work of every increment is
+ * enqueued: the batched device-wide solver (increments above 8 active
+ * orbitals) enqueues max_iter iterations' worth of launches, each a no-op
+ * once every increment has stopped, instead of the host checking the number
+ * of live increments between groups of iterations. */
+#define IFCI_FLAG_ASYNC_WIDE 1u
 
 /* Version of this header the library was built from (IFCI_ABI_VERSION). */
 int ifci_abi_version(void);

@@ -63,6 +63,28 @@ void free_one(T*& p) {
   p = nullptr;
 }
 
+// Free what earlier batched device-wide solves kept alive (graphs, host
+// copies of uploaded arrays) once their work has run; `all` waits for it.
+void release_in_flight(ifci_plan_s* P, bool all) {
+  std::vector<ifci_plan_s::InFlight> keep;
+  for (ifci_plan_s::InFlight& f : P->in_flight) {
+    bool done = true;
+    if (f.done) {
+      if (all)
+        (void)hipEventSynchronize(f.done);
+      else
+        done = hipEventQuery(f.done) == hipSuccess;
+    }
+    if (!done) {
+      keep.push_back(std::move(f));
+      continue;
+    }
+    for (hipGraphExec_t g : f.graphs) (void)hipGraphExecDestroy(g);
+    if (f.done) (void)hipEventDestroy(f.done);
+  }
+  P->in_flight = std::move(keep);
+}
+
 void free_device(ifci_plan_s* P) {
   free_one(P->d_inc);
   free_one(P->d_orbs);
@@ -74,6 +96,15 @@ void free_device(ifci_plan_s* P) {
   free_one(P->d_rdm_off);
   free_one(P->d_loc);
   free_one(P->d_w_inc);
+  release_in_flight(P, true);
+  if (P->capture_stream) (void)hipStreamDestroy(P->capture_stream);
+  P->capture_stream = nullptr;
+  for (hipEvent_t& e : P->poll_event) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
+  if (P->pinned) (void)hipHostFree(P->pinned);
+  P->pinned = nullptr;
   for (hipStream_t s : P->slot_streams) (void)hipStreamDestroy(s);
   for (hipEvent_t e : P->slot_events) (void)hipEventDestroy(e);
   if (P->fork_event) (void)hipEventDestroy(P->fork_event);
@@ -140,6 +171,138 @@ int batch_lds(const ifci_plan_s* P, const std::vector<int32_t>& ids) {
     need = std::max(need, batched_lds_want(d.k, d.n_str, d.n_link));
   }
   return (int)std::min<int64_t>(kMaxLds, (need + 255) & ~int64_t(255));
+}
+
+// Iterations captured per graph of the batched device-wide solver; without
+// IFCI_FLAG_ASYNC_WIDE the host reads the live count after every graph (one
+// graph behind the device).
+constexpr int kWideChunk = 4;
+
+// Copy of v kept in `keep`; returns the copy's bytes (stable: moving the
+// outer vector does not move them).
+template <typename T>
+const char* push_bytes(std::vector<std::vector<char>>& keep, const std::vector<T>& v) {
+  keep.emplace_back((const char*)v.data(), (const char*)v.data() + v.size() * sizeof(T));
+  return keep.back().data();
+}
+
+// The increments `ids` (not on chip) by the batched device-wide solver:
+// grouped by shape, at most wide_cap at a time, each group set up, iterated
+// with device-side control (graph replays of kWideChunk iterations) and its
+// outputs written.
+ifci_status run_wide(ifci_plan_s* P, const std::vector<int32_t>& ids, int64_t first, double* e_out,
+                     int32_t* status_out, int32_t* iters_out, double* resid_out, const uint8_t* evict_mask,
+                     hipStream_t st) {
+  release_in_flight(P, false);
+  if (P->wide_cap < 1) {
+    set_error("ifci_davidson: the workspace has no slots for device-wide increments");
+    return IFCI_ERR_STATE;
+  }
+  HIP_TRY(wide_prepare(0), "ifci_davidson wide");
+  if (!P->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&P->capture_stream, hipStreamNonBlocking), "stream");
+  if (!P->pinned) HIP_TRY(hipHostMalloc((void**)&P->pinned, 2 * sizeof(int32_t), hipHostMallocDefault), "pinned");
+  for (hipEvent_t& e : P->poll_event)
+    if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+  const bool async = (P->opt.flags & IFCI_FLAG_ASYNC_WIDE) != 0;
+  ifci_plan_s::InFlight fl;
+  // shape groups, in the order given (heaviest first)
+  std::vector<std::pair<std::pair<int, int>, std::vector<int32_t>>> groups;
+  for (int32_t i : ids) {
+    const std::pair<int, int> key(P->inc[i].k, P->inc[i].na);
+    size_t g = 0;
+    while (g < groups.size() && groups[g].first != key) ++g;
+    if (g == groups.size()) groups.push_back({key, {}});
+    groups[g].second.push_back(i);
+  }
+  char* ctl_base = P->ws + P->off_wide_ctl;
+  const int cap = P->wide_cap;
+  WideItem* d_items = (WideItem*)ctl_base;
+  WideItem** d_ptrs = (WideItem**)(ctl_base + ((int64_t)cap * sizeof(WideItem) + 255) / 256 * 256);
+  int* d_ctl = (int*)((char*)d_ptrs + ((int64_t)cap * 8 + 255) / 256 * 256);
+  int32_t* d_pos = (int32_t*)((char*)d_ctl + ((int64_t)wide_ctl_ints(cap) * 4 + 255) / 256 * 256);
+  for (auto& grp : groups) {
+    const std::vector<int32_t>& all = grp.second;
+    for (size_t g0 = 0; g0 < all.size(); g0 += (size_t)cap) {
+      const int n = (int)std::min<size_t>((size_t)cap, all.size() - g0);
+      std::vector<WideItem> items(n);
+      std::vector<WideItem*> ptrs(n);
+      std::vector<int32_t> pos(n);
+      for (int j = 0; j < n; ++j) {
+        const int32_t i = all[g0 + j];
+        const IncDev& d = P->inc[i];
+        const WideSlot sl = wide_slot(d);
+        double* slot = (double*)(P->ws + P->off_wide) + (int64_t)j * P->wide_slot_doubles;
+        WideItem& w = items[j];
+        std::memset(&w, 0, sizeof(w));
+        w.d = d;
+        w.B = P->ws_ints() + d.int_off;
+        w.tabs = P->d_tables;
+        w.Vb = P->ws_dav() + d.vec_off;
+        w.Sb = w.Vb + (int64_t)d.mspace * d.stride;
+        w.HD = w.Vb + 2 * (int64_t)d.mspace * d.stride;
+        w.X = w.HD + d.stride;
+        w.T = slot + sl.T;
+        w.F = slot + sl.F;
+        w.part = slot + sl.part;
+        w.state = slot + sl.state;
+        w.sc = slot + sl.sc;
+        w.evict = evict_mask ? evict_mask + (i - first) : nullptr;
+        w.mmax = d.mspace;
+        ptrs[j] = d_items + j;
+        pos[j] = (int32_t)(i - first);
+      }
+      // the copies read host memory that stays alive until this call's
+      // work has run (released by a later call or at plan destruction)
+      const char* h_items = push_bytes(fl.host, items);
+      const char* h_ptrs = push_bytes(fl.host, ptrs);
+      const char* h_pos = push_bytes(fl.host, pos);
+      HIP_TRY(hipMemcpyAsync(d_items, h_items, n * sizeof(WideItem), hipMemcpyHostToDevice, st), "upload");
+      HIP_TRY(hipMemcpyAsync(d_ptrs, h_ptrs, n * sizeof(WideItem*), hipMemcpyHostToDevice, st), "upload");
+      HIP_TRY(hipMemcpyAsync(d_pos, h_pos, n * sizeof(int32_t), hipMemcpyHostToDevice, st), "upload");
+      WideRun R;
+      R.items = d_ptrs;
+      R.n = n;
+      R.ctl = d_ctl;
+      R.d = P->inc[all[g0]];
+      R.k = R.d.k;
+      R.precision = P->opt.precision;
+      R.max_iter = P->opt.max_iter;
+      R.r_tol = P->opt.r_tol;
+      R.r_tol_inner = P->opt.r_tol_inner;
+      HIP_TRY(wide_setup(R, st), "ifci_davidson wide set-up");
+      // one chunk of iterations, captured once and replayed
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      HIP_TRY(hipStreamBeginCapture(P->capture_stream, hipStreamCaptureModeThreadLocal), "capture");
+      hipError_t ce = hipSuccess;
+      for (int c = 0; c < kWideChunk && ce == hipSuccess; ++c) ce = wide_iteration(R, P->capture_stream);
+      const hipError_t ee = hipStreamEndCapture(P->capture_stream, &graph);
+      HIP_TRY(ce, "ifci_davidson wide capture");
+      HIP_TRY(ee, "ifci_davidson wide capture");
+      const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      HIP_TRY(ie, "ifci_davidson wide instantiate");
+      fl.graphs.push_back(exec);
+      const int n_chunks = (R.max_iter + kWideChunk) / kWideChunk;  // at least max_iter + 1 iterations
+      for (int c = 0; c < n_chunks; ++c) {
+        HIP_TRY(hipGraphLaunch(exec, st), "ifci_davidson wide launch");
+        if (async) continue;
+        HIP_TRY(hipMemcpyAsync(P->pinned + (c & 1), d_ctl + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+                "ifci_davidson live count");
+        HIP_TRY(hipEventRecord(P->poll_event[c & 1], st), "ifci_davidson");
+        if (c >= 1) {
+          HIP_TRY(hipEventSynchronize(P->poll_event[(c - 1) & 1]), "ifci_davidson");
+          if (P->pinned[(c - 1) & 1] == 0) break;
+        }
+      }
+      HIP_TRY(wide_finish(d_ptrs, n, d_pos, P->e_const, e_out, status_out, iters_out, resid_out, st),
+              "ifci_davidson wide finish");
+    }
+  }
+  HIP_TRY(hipEventCreateWithFlags(&fl.done, hipEventDisableTiming), "event");
+  HIP_TRY(hipEventRecord(fl.done, st), "event");
+  P->in_flight.push_back(std::move(fl));
+  return IFCI_OK;
 }
 
 }  // namespace
@@ -447,7 +610,10 @@ ifci_status ifci_davidson(ifci_plan_t p, int64_t first, int64_t count, double* e
     A.phase = p->phase_counters;
     HIP_TRY(launch_batched(A, batch_lds(p, ids), st), "ifci_davidson batched");
   }
-  if (!rest.empty()) {
+  if (!rest.empty() && !plain_only) {
+    s = run_wide(p, rest, first, e_out, status_out, iters_out, resid_out, evict_mask, st);
+    if (s != IFCI_OK) return s;
+  } else if (!rest.empty()) {
     std::vector<uint8_t> ev;
     if (evict_mask) {
       ev.resize(count);

@@ -57,6 +57,50 @@ hipError_t run_plain(const PlainArgs& A, double* e_out, int32_t* status_out, int
 
 hipError_t launch_expand(const IncDev& d, const double* X, double* c, hipStream_t st);
 
+// ---------------------------------------------------------------- batched device-wide solver
+// One increment of the batched device-wide Davidson (wide.hip).  Pointers
+// are device addresses: the increment's integral block and tables, its
+// Davidson block (basis, sigma, diagonal, Ritz vector), and its slot of the
+// solver region (temporaries, partial sums, state, sigma scratch).
+struct WideItem {
+  IncDev d;
+  const double* B;
+  const int32_t* tabs;
+  double* Vb;
+  double* Sb;
+  double* HD;
+  double* X;
+  double* T;
+  double* F;
+  double* part;
+  double* state;          // a DavState
+  double* sc;             // sigma scratch
+  const uint8_t* evict;   // nonzero byte: stop after one iteration (EVICTED); may be null
+  int32_t mmax;
+  int32_t pad;
+};
+
+// One batch: n increments of one shape (d), their items (device array of
+// pointers), a control block of wide_ctl_ints(n) ints (live counts and
+// lists).
+struct WideRun {
+  WideItem* const* items;
+  int n;
+  int* ctl;
+  IncDev d;
+  int k;
+  int precision, max_iter;
+  double r_tol, r_tol_inner;
+};
+int64_t wide_sigma_scratch_doubles(const IncDev& d);
+int64_t wide_part_doubles(const IncDev& d);
+int wide_ctl_ints(int n);
+hipError_t wide_prepare(int k);                          // kernel attributes (current device)
+hipError_t wide_setup(const WideRun& R, hipStream_t s);      // diagonal, guess, state, fragments, lists
+hipError_t wide_iteration(const WideRun& R, hipStream_t s);  // one iteration's launches (capturable)
+hipError_t wide_finish(WideItem* const* items, int n, const int32_t* out_pos, double e_const, double* e_out,
+                       int32_t* status_out, int32_t* iters_out, double* resid_out, hipStream_t s);
+
 hipError_t launch_energy(const double* e_inc, const int32_t* status, const int32_t* sub_ptr,
                          const int32_t* sub_idx, const int32_t* inc_size, int n_inc, int order,
                          const double* misc_in, double* eps, double* out, int32_t* bad,

@@ -136,6 +136,23 @@ using namespace ifci;
 
 static int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+namespace ifci {
+WideSlot wide_slot(const IncDev& d) {
+  WideSlot w;
+  w.T = 0;
+  w.F = align_up(d.stride, 32);
+  w.part = w.F + align_up(d.n_str, 32);
+  w.state = w.part + align_up(wide_part_doubles(d), 32);
+  w.sc = w.state + 4096;
+  return w;
+}
+int64_t wide_slot_doubles(const IncDev& d) { return wide_slot(d).sc + wide_sigma_scratch_doubles(d); }
+int64_t wide_ctl_bytes(int cap) {
+  return align_up((int64_t)cap * sizeof(WideItem), 256) + align_up((int64_t)cap * 8, 256) +
+         align_up((int64_t)wide_ctl_ints(cap) * 4, 256) + align_up((int64_t)cap * 4, 256);
+}
+}  // namespace ifci
+
 // Builds everything host-side.  Returns IFCI_OK or an error with message set.
 ifci_status plan_build(ifci_plan_s* P, const ifci_problem* pr, const ifci_options* op) {
   if (!pr || !pr->body_ptr || !pr->body_orb || !pr->body_nocc) {
@@ -313,10 +330,12 @@ ifci_status plan_build(ifci_plan_s* P, const ifci_problem* pr, const ifci_option
   // device-wide solves run several increments at once when their scratch is
   // small: up to 8 slots within 2 GiB of E scratch beyond the first, and no
   // more slots than increments that can take that path
+  // (the plain solver's per-increment loops; the batched solver needs one
+  // slot, for ifci_sigma and ifci_sigma_sector)
   {
     int64_t n_wide = 0;
     for (const ifci::IncDev& d : P->inc)
-      if (op->solver == IFCI_SOLVER_PLAIN || d.k > 8) ++n_wide;
+      if (op->solver == IFCI_SOLVER_PLAIN) ++n_wide;
     const int64_t by_mem = 1 + ((int64_t)2 << 30) / std::max<int64_t>(1, P->E_doubles * 8);
     P->n_slots = (int)std::max<int64_t>(1, std::min<int64_t>({8, by_mem, n_wide}));
   }
@@ -330,6 +349,30 @@ ifci_status plan_build(ifci_plan_s* P, const ifci_problem* pr, const ifci_option
   off = align_up(off + P->n_slots * P->part_doubles * 8, A);
   P->off_state = off;
   off = align_up(off + P->n_slots * 4096 * 8, A);
+  // batched device-wide solver: one slot per increment it runs at once
+  // (temporaries, partial sums, state, sigma scratch), up to kWideBudget
+  // bytes of slots, and the control block (items, their pointers, live
+  // lists, output positions)
+  {
+    int64_t slot = 0, n_wide = 0;
+    for (const ifci::IncDev& d : P->inc) {
+      const bool on_chip = op->solver != IFCI_SOLVER_PLAIN && d.k <= 8 &&
+                           ifci::batched_lds_bytes(d.k, d.n_str, d.n_link) <= ifci::kMaxLds;
+      if (on_chip || op->solver == IFCI_SOLVER_PLAIN) continue;
+      ++n_wide;
+      slot = std::max(slot, wide_slot_doubles(d));
+    }
+    P->wide_slot_doubles = align_up(slot, 32);
+    P->wide_cap = 0;
+    if (n_wide > 0) {
+      const int64_t by_mem = std::max<int64_t>(1, kWideBudget / (P->wide_slot_doubles * 8));
+      P->wide_cap = (int)std::min<int64_t>(n_wide, by_mem);
+    }
+    P->off_wide = off;
+    off = align_up(off + (int64_t)P->wide_cap * P->wide_slot_doubles * 8, A);
+    P->off_wide_ctl = off;
+    off = align_up(off + wide_ctl_bytes(P->wide_cap), A);
+  }
   P->off_rdm = off;
   off = align_up(off + P->rdm_doubles * 8, A);
   P->off_misc = off;

@@ -5,6 +5,8 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_runtime.h>
+
 #include "ifci_internal.h"
 
 struct ifci_plan_s {
@@ -39,6 +41,20 @@ struct ifci_plan_s {
   std::vector<hipStream_t> slot_streams;
   std::vector<hipEvent_t> slot_events;
   hipEvent_t fork_event = nullptr;
+  // batched device-wide solver: region of wide_cap slots, control block,
+  // and what the calls in flight keep alive (host copies of uploaded
+  // arrays, graphs) until their work has run
+  int64_t off_wide = 0, off_wide_ctl = 0, wide_slot_doubles = 0;
+  int wide_cap = 0;
+  hipStream_t capture_stream = nullptr;
+  int32_t* pinned = nullptr;  // 2 ints of host memory the live counts are copied to
+  hipEvent_t poll_event[2] = {nullptr, nullptr};
+  struct InFlight {
+    hipEvent_t done = nullptr;
+    std::vector<hipGraphExec_t> graphs;
+    std::vector<std::vector<char>> host;
+  };
+  std::vector<InFlight> in_flight;
   // device
   ifci::IncDev* d_inc = nullptr;
   int32_t* d_orbs = nullptr;
@@ -93,3 +109,16 @@ void fill_link_dump(int k, int na, int32_t* strings, int32_t* link);
 }  // namespace ifci
 
 ifci_status plan_build(ifci_plan_s* P, const ifci_problem* pr, const ifci_options* op);
+
+namespace ifci {
+// bytes of slots the batched device-wide solver may take in a workspace
+constexpr int64_t kWideBudget = (int64_t)32 << 30;
+// doubles of one slot of that solver for increment d: preconditioned
+// residual, string energies, partial sums, state, sigma scratch
+int64_t wide_slot_doubles(const IncDev& d);
+struct WideSlot {
+  int64_t T, F, part, state, sc;
+};
+WideSlot wide_slot(const IncDev& d);
+int64_t wide_ctl_bytes(int cap);
+}  // namespace ifci

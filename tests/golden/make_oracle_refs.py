@@ -122,10 +122,15 @@ def main():
     todo["chain4_full"] = (p4, ifci.increments(4, 4), True)
     p2 = synthetic.workload(2)
     inc2 = ifci.increments(p2.n_bodies, p2.order)
-    sample = [S for S in inc2 if len(S) <= 2] + [S for S in inc2 if len(S) == 3][::28] + \
-             [S for S in inc2 if len(S) == 4][::91]
-    todo["w2_sample"] = (p2, sample, False)
     todo["w2"] = (p2, inc2, True)
+    # shapes above 8 active orbitals away from half filling, which take the
+    # device-wide solver's general (materialised) product: 9 orbitals with 6
+    # electrons (three bodies of 3 orbitals, one doubly occupied each) and 12
+    # orbitals with 4 electrons (two bodies of 6 orbitals, one occupied each)
+    p9 = synthetic.chain(3, orbs_per_body=3, nocc_per_body=1, seed=3093, order=3)
+    todo["wide_9o6e"] = (p9, ifci.increments(3, 3), True)
+    p12 = synthetic.chain(2, orbs_per_body=6, nocc_per_body=1, seed=3124, order=2)
+    todo["wide_12o4e"] = (p12, ifci.increments(2, 2), True)
     for name, (p, subsets, full) in todo.items():
         if a.only and a.only != name:
             continue
