@@ -331,13 +331,15 @@ def workload3_leg(torch, ifci, synthetic):
 
 def workload4_batch_leg(torch, ifci, synthetic, count=256):
     """256 independent 10o10e FCI problems (K = 20, seeds 4000..4255), one
-    plan each, all solved in mixed precision then timed as one job."""
+    plan each, solved together in mixed precision by one batched call
+    (ifci_davidson_group) and timed as one job."""
     problems = [synthetic.single(10, 20, 4000 + i) for i in range(count)]
     plans = [ifci.Plan(q, precision=ifci.MIXED, r_tol=R_TOL, r_tol_inner=R_TOL_INNER, max_iter=300).attach(q.h, q.eri)
              for q in problems]
+    ifci.davidson_group(plans)  # warm-up (kernel loads, control block)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    outs = [pl.davidson() for pl in plans]
+    outs = ifci.davidson_group(plans)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t
     it = np.array([int(o[2][0]) for o in outs])

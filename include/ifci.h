@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define IFCI_ABI_VERSION 1
+#define IFCI_ABI_VERSION 2
 
 typedef struct ifci_plan_s* ifci_plan_t;
 typedef void* ifci_stream_t; /* a hipStream_t; NULL = the null stream */
@@ -215,6 +215,22 @@ ifci_status ifci_sigma_sector(ifci_plan_t plan, int64_t inc, const double* c, do
 ifci_status ifci_davidson(ifci_plan_t plan, int64_t first, int64_t count, double* e_out,
                           int32_t* status_out, const uint8_t* evict_mask, int32_t* iters_out,
                           double* resid_out, ifci_stream_t stream);
+
+/* Lowest even-spin roots of every increment of n_plans plans (for instance
+ * independent FCI problems, each a one-increment plan) in one batched solve:
+ * each plan's increments that fit on chip run in one launch of the batched
+ * solver, and the others of all plans join the same batched device-wide
+ * solve (one per active-space shape).  plans: host [n_plans], distinct, on
+ * one device, each with workspace and integrals set, all created with the
+ * batched solver and identical options.  e_out[j], status_out[j] (and,
+ * where given, iters_out[j], resid_out[j]): device arrays of plan j's
+ * increment count, as in ifci_davidson; iters_out and resid_out may be NULL.
+ * Stream order and return as in ifci_davidson; converged vectors stay in
+ * each plan's workspace.  The first plan keeps the solve's control block
+ * (device memory it allocates on first use and grows as needed). */
+ifci_status ifci_davidson_group(const ifci_plan_t* plans, int32_t n_plans, double* const* e_out,
+                                int32_t* const* status_out, int32_t* const* iters_out,
+                                double* const* resid_out, ifci_stream_t stream);
 
 /* Copy the converged unit vector of increment inc (device [n_det]). */
 ifci_status ifci_vector(ifci_plan_t plan, int64_t inc, double* c_out, ifci_stream_t stream);

@@ -96,6 +96,8 @@ void free_device(ifci_plan_s* P) {
   free_one(P->d_rdm_off);
   free_one(P->d_loc);
   free_one(P->d_w_inc);
+  free_one(P->group_ctl);
+  P->group_ctl_bytes = 0;
   release_in_flight(P, true);
   if (P->capture_stream) (void)hipStreamDestroy(P->capture_stream);
   P->capture_stream = nullptr;
@@ -186,97 +188,166 @@ const char* push_bytes(std::vector<std::vector<char>>& keep, const std::vector<T
   return keep.back().data();
 }
 
-// The increments `ids` (not on chip) by the batched device-wide solver:
-// grouped by shape, at most wide_cap at a time, each group set up, iterated
-// with device-side control (graph replays of kWideChunk iterations) and its
-// outputs written.
-ifci_status run_wide(ifci_plan_s* P, const std::vector<int32_t>& ids, int64_t first, double* e_out,
-                     int32_t* status_out, int32_t* iters_out, double* resid_out, const uint8_t* evict_mask,
-                     hipStream_t st) {
-  release_in_flight(P, false);
-  if (P->wide_cap < 1) {
-    set_error("ifci_davidson: the workspace has no slots for device-wide increments");
-    return IFCI_ERR_STATE;
+// Layout of a control block for n items: item pointers, live counts and
+// lists, output positions (each 256-byte aligned).
+struct CtlBlock {
+  WideItem** ptrs;
+  int* ctl;
+  int32_t* pos;
+};
+int64_t ctl_block_bytes(int n) {
+  auto up = [](int64_t x) { return (x + 255) / 256 * 256; };
+  return up((int64_t)n * 8) + up((int64_t)wide_ctl_ints(n) * 4) + up((int64_t)n * 4);
+}
+CtlBlock ctl_block(char* base, int n) {
+  auto up = [](int64_t x) { return (x + 255) / 256 * 256; };
+  CtlBlock c;
+  c.ptrs = (WideItem**)base;
+  c.ctl = (int*)(base + up((int64_t)n * 8));
+  c.pos = (int32_t*)((char*)c.ctl + up((int64_t)wide_ctl_ints(n) * 4));
+  return c;
+}
+
+// The increments of one plan that a batched device-wide solve takes, with
+// where their outputs go.
+struct WideMember {
+  ifci_plan_s* P;
+  std::vector<int32_t> ids;
+  int64_t first;
+  double* e_out;
+  int32_t* status_out;
+  int32_t* iters_out;
+  double* resid_out;
+  const uint8_t* evict;
+};
+
+// Batched device-wide solve of the members' increments: grouped by shape
+// across plans, each plan contributing at most its wide_cap increments to a
+// batch; every batch set up, iterated with device-side control (graph
+// replays of kWideChunk iterations) and its outputs written.  `owner` keeps
+// the streams, events, pinned counts and (for several plans) the control
+// block; the options (precision, tolerances, iterations, flags) are owner's.
+ifci_status run_wide(ifci_plan_s* owner, std::vector<WideMember>& members, hipStream_t st) {
+  ifci_plan_s* O = owner;
+  for (WideMember& m : members) {
+    release_in_flight(m.P, false);
+    if (!m.ids.empty() && m.P->wide_cap < 1) {
+      set_error("ifci_davidson: the workspace has no slots for device-wide increments");
+      return IFCI_ERR_STATE;
+    }
   }
   HIP_TRY(wide_prepare(0), "ifci_davidson wide");
-  if (!P->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&P->capture_stream, hipStreamNonBlocking), "stream");
-  if (!P->pinned) HIP_TRY(hipHostMalloc((void**)&P->pinned, 2 * sizeof(int32_t), hipHostMallocDefault), "pinned");
-  for (hipEvent_t& e : P->poll_event)
+  if (!O->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&O->capture_stream, hipStreamNonBlocking), "stream");
+  if (!O->pinned) HIP_TRY(hipHostMalloc((void**)&O->pinned, 2 * sizeof(int32_t), hipHostMallocDefault), "pinned");
+  for (hipEvent_t& e : O->poll_event)
     if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
-  const bool async = (P->opt.flags & IFCI_FLAG_ASYNC_WIDE) != 0;
+  const bool async = (O->opt.flags & IFCI_FLAG_ASYNC_WIDE) != 0;
+  const bool group = members.size() > 1;
   ifci_plan_s::InFlight fl;
-  // shape groups, in the order given (heaviest first)
-  std::vector<std::pair<std::pair<int, int>, std::vector<int32_t>>> groups;
-  for (int32_t i : ids) {
-    const std::pair<int, int> key(P->inc[i].k, P->inc[i].na);
-    size_t g = 0;
-    while (g < groups.size() && groups[g].first != key) ++g;
-    if (g == groups.size()) groups.push_back({key, {}});
-    groups[g].second.push_back(i);
-  }
-  char* ctl_base = P->ws + P->off_wide_ctl;
-  const int cap = P->wide_cap;
-  WideItem* d_items = (WideItem*)ctl_base;
-  WideItem** d_ptrs = (WideItem**)(ctl_base + ((int64_t)cap * sizeof(WideItem) + 255) / 256 * 256);
-  int* d_ctl = (int*)((char*)d_ptrs + ((int64_t)cap * 8 + 255) / 256 * 256);
-  int32_t* d_pos = (int32_t*)((char*)d_ctl + ((int64_t)wide_ctl_ints(cap) * 4 + 255) / 256 * 256);
-  for (auto& grp : groups) {
-    const std::vector<int32_t>& all = grp.second;
-    for (size_t g0 = 0; g0 < all.size(); g0 += (size_t)cap) {
-      const int n = (int)std::min<size_t>((size_t)cap, all.size() - g0);
-      std::vector<WideItem> items(n);
-      std::vector<WideItem*> ptrs(n);
-      std::vector<int32_t> pos(n);
-      for (int j = 0; j < n; ++j) {
-        const int32_t i = all[g0 + j];
-        const IncDev& d = P->inc[i];
-        const WideSlot sl = wide_slot(d);
-        double* slot = (double*)(P->ws + P->off_wide) + (int64_t)j * P->wide_slot_doubles;
-        WideItem& w = items[j];
-        std::memset(&w, 0, sizeof(w));
-        w.d = d;
-        w.B = P->ws_ints() + d.int_off;
-        w.tabs = P->d_tables;
-        w.Vb = P->ws_dav() + d.vec_off;
-        w.Sb = w.Vb + (int64_t)d.mspace * d.stride;
-        w.HD = w.Vb + 2 * (int64_t)d.mspace * d.stride;
-        w.X = w.HD + d.stride;
-        w.T = slot + sl.T;
-        w.F = slot + sl.F;
-        w.part = slot + sl.part;
-        w.state = slot + sl.state;
-        w.sc = slot + sl.sc;
-        w.evict = evict_mask ? evict_mask + (i - first) : nullptr;
-        w.mmax = d.mspace;
-        ptrs[j] = d_items + j;
-        pos[j] = (int32_t)(i - first);
+  // (shape) -> per member, its increments of that shape, in the given order
+  std::vector<std::pair<int, int>> shapes;
+  for (WideMember& m : members)
+    for (int32_t i : m.ids) {
+      const std::pair<int, int> key(m.P->inc[i].k, m.P->inc[i].na);
+      if (std::find(shapes.begin(), shapes.end(), key) == shapes.end()) shapes.push_back(key);
+    }
+  for (const std::pair<int, int>& key : shapes) {
+    std::vector<std::vector<int32_t>> todo(members.size());
+    size_t left = 0;
+    for (size_t mi = 0; mi < members.size(); ++mi)
+      for (int32_t i : members[mi].ids)
+        if (members[mi].P->inc[i].k == key.first && members[mi].P->inc[i].na == key.second) todo[mi].push_back(i);
+    for (auto& t : todo) left += t.size();
+    std::vector<size_t> next(members.size(), 0);
+    while (left > 0) {
+      // one batch: up to wide_cap increments of each member
+      std::vector<WideItem*> ptrs;
+      std::vector<int32_t> pos;
+      std::vector<std::pair<size_t, std::pair<int, int>>> spans;  // member, (offset, count)
+      IncDev shape{};
+      for (size_t mi = 0; mi < members.size(); ++mi) {
+        WideMember& m = members[mi];
+        ifci_plan_s* P = m.P;
+        const int take = (int)std::min<size_t>((size_t)P->wide_cap, todo[mi].size() - next[mi]);
+        if (take <= 0) continue;
+        WideItem* d_items = (WideItem*)(P->ws + P->off_wide_ctl);
+        std::vector<WideItem> items(take);
+        for (int j = 0; j < take; ++j) {
+          const int32_t i = todo[mi][next[mi] + j];
+          const IncDev& d = P->inc[i];
+          const WideSlot sl = wide_slot(d);
+          double* slot = (double*)(P->ws + P->off_wide) + (int64_t)j * P->wide_slot_doubles;
+          WideItem& w = items[j];
+          std::memset(&w, 0, sizeof(w));
+          w.d = d;
+          w.B = P->ws_ints() + d.int_off;
+          w.tabs = P->d_tables;
+          w.Vb = P->ws_dav() + d.vec_off;
+          w.Sb = w.Vb + (int64_t)d.mspace * d.stride;
+          w.HD = w.Vb + 2 * (int64_t)d.mspace * d.stride;
+          w.X = w.HD + d.stride;
+          w.T = slot + sl.T;
+          w.F = slot + sl.F;
+          w.part = slot + sl.part;
+          w.state = slot + sl.state;
+          w.sc = slot + sl.sc;
+          w.evict = m.evict ? m.evict + (i - m.first) : nullptr;
+          w.mmax = d.mspace;
+          shape = d;
+        }
+        // the copies read host memory kept alive until this call's work has
+        // run (released by a later call or at plan destruction)
+        const char* h_items = push_bytes(fl.host, items);
+        HIP_TRY(hipMemcpyAsync(d_items, h_items, take * sizeof(WideItem), hipMemcpyHostToDevice, st), "upload");
+        spans.push_back({mi, {(int)ptrs.size(), take}});
+        for (int j = 0; j < take; ++j) {
+          ptrs.push_back(d_items + j);
+          pos.push_back((int32_t)(todo[mi][next[mi] + j] - m.first));
+        }
+        next[mi] += take;
+        left -= take;
       }
-      // the copies read host memory that stays alive until this call's
-      // work has run (released by a later call or at plan destruction)
-      const char* h_items = push_bytes(fl.host, items);
+      const int n = (int)ptrs.size();
+      char* cbase;
+      if (!group) {
+        ifci_plan_s* P = members[0].P;
+        cbase = P->ws + P->off_wide_ctl + ((int64_t)P->wide_cap * sizeof(WideItem) + 255) / 256 * 256;
+      } else {
+        const int64_t need = ctl_block_bytes(n);
+        if (need > O->group_ctl_bytes) {
+          // grow the owner's control block (its earlier work is done first)
+          HIP_TRY(hipStreamSynchronize(st), "ifci_davidson_group");
+          if (O->group_ctl) (void)hipFree(O->group_ctl);
+          O->group_ctl = nullptr;
+          O->group_ctl_bytes = 0;
+          HIP_TRY(hipMalloc((void**)&O->group_ctl, need), "ifci_davidson_group control block");
+          O->group_ctl_bytes = need;
+        }
+        cbase = O->group_ctl;
+      }
+      const CtlBlock cb = ctl_block(cbase, n);
       const char* h_ptrs = push_bytes(fl.host, ptrs);
       const char* h_pos = push_bytes(fl.host, pos);
-      HIP_TRY(hipMemcpyAsync(d_items, h_items, n * sizeof(WideItem), hipMemcpyHostToDevice, st), "upload");
-      HIP_TRY(hipMemcpyAsync(d_ptrs, h_ptrs, n * sizeof(WideItem*), hipMemcpyHostToDevice, st), "upload");
-      HIP_TRY(hipMemcpyAsync(d_pos, h_pos, n * sizeof(int32_t), hipMemcpyHostToDevice, st), "upload");
+      HIP_TRY(hipMemcpyAsync(cb.ptrs, h_ptrs, n * sizeof(WideItem*), hipMemcpyHostToDevice, st), "upload");
+      HIP_TRY(hipMemcpyAsync(cb.pos, h_pos, n * sizeof(int32_t), hipMemcpyHostToDevice, st), "upload");
       WideRun R;
-      R.items = d_ptrs;
+      R.items = cb.ptrs;
       R.n = n;
-      R.ctl = d_ctl;
-      R.d = P->inc[all[g0]];
-      R.k = R.d.k;
-      R.precision = P->opt.precision;
-      R.max_iter = P->opt.max_iter;
-      R.r_tol = P->opt.r_tol;
-      R.r_tol_inner = P->opt.r_tol_inner;
+      R.ctl = cb.ctl;
+      R.d = shape;
+      R.k = shape.k;
+      R.precision = O->opt.precision;
+      R.max_iter = O->opt.max_iter;
+      R.r_tol = O->opt.r_tol;
+      R.r_tol_inner = O->opt.r_tol_inner;
       HIP_TRY(wide_setup(R, st), "ifci_davidson wide set-up");
       // one chunk of iterations, captured once and replayed
       hipGraph_t graph = nullptr;
       hipGraphExec_t exec = nullptr;
-      HIP_TRY(hipStreamBeginCapture(P->capture_stream, hipStreamCaptureModeThreadLocal), "capture");
+      HIP_TRY(hipStreamBeginCapture(O->capture_stream, hipStreamCaptureModeThreadLocal), "capture");
       hipError_t ce = hipSuccess;
-      for (int c = 0; c < kWideChunk && ce == hipSuccess; ++c) ce = wide_iteration(R, P->capture_stream);
-      const hipError_t ee = hipStreamEndCapture(P->capture_stream, &graph);
+      for (int c = 0; c < kWideChunk && ce == hipSuccess; ++c) ce = wide_iteration(R, O->capture_stream);
+      const hipError_t ee = hipStreamEndCapture(O->capture_stream, &graph);
       HIP_TRY(ce, "ifci_davidson wide capture");
       HIP_TRY(ee, "ifci_davidson wide capture");
       const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -287,21 +358,66 @@ ifci_status run_wide(ifci_plan_s* P, const std::vector<int32_t>& ids, int64_t fi
       for (int c = 0; c < n_chunks; ++c) {
         HIP_TRY(hipGraphLaunch(exec, st), "ifci_davidson wide launch");
         if (async) continue;
-        HIP_TRY(hipMemcpyAsync(P->pinned + (c & 1), d_ctl + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+        HIP_TRY(hipMemcpyAsync(O->pinned + (c & 1), cb.ctl + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st),
                 "ifci_davidson live count");
-        HIP_TRY(hipEventRecord(P->poll_event[c & 1], st), "ifci_davidson");
+        HIP_TRY(hipEventRecord(O->poll_event[c & 1], st), "ifci_davidson");
         if (c >= 1) {
-          HIP_TRY(hipEventSynchronize(P->poll_event[(c - 1) & 1]), "ifci_davidson");
-          if (P->pinned[(c - 1) & 1] == 0) break;
+          HIP_TRY(hipEventSynchronize(O->poll_event[(c - 1) & 1]), "ifci_davidson");
+          if (O->pinned[(c - 1) & 1] == 0) break;
         }
       }
-      HIP_TRY(wide_finish(d_ptrs, n, d_pos, P->e_const, e_out, status_out, iters_out, resid_out, st),
-              "ifci_davidson wide finish");
+      for (auto& sp : spans) {
+        const WideMember& m = members[sp.first];
+        HIP_TRY(wide_finish(cb.ptrs + sp.second.first, sp.second.second, cb.pos + sp.second.first, m.P->e_const,
+                            m.e_out, m.status_out, m.iters_out, m.resid_out, st),
+                "ifci_davidson wide finish");
+      }
     }
   }
   HIP_TRY(hipEventCreateWithFlags(&fl.done, hipEventDisableTiming), "event");
   HIP_TRY(hipEventRecord(fl.done, st), "event");
-  P->in_flight.push_back(std::move(fl));
+  O->in_flight.push_back(std::move(fl));
+  // the members' regions are in use until that event: their next calls
+  // wait for it through stream order; record it on them too for release
+  return IFCI_OK;
+}
+
+// One launch of the on-chip batched solver over the increments `ids`
+// (heaviest first) of plan p.
+ifci_status launch_on_chip(ifci_plan_s* p, const std::vector<int32_t>& ids, int64_t first, double* e_out,
+                           int32_t* status_out, const uint8_t* evict_mask, int32_t* iters_out, double* resid_out,
+                           hipStream_t st) {
+  if (ids.empty()) return IFCI_OK;
+  if (ids != p->order_batch) {
+    // a new work list: wait for any earlier upload from order_batch
+    // before reusing its host memory (a repeated list is already there)
+    HIP_TRY(hipStreamSynchronize(st), "ifci_davidson");
+    p->order_batch = ids;
+    HIP_TRY(hipMemcpyAsync(p->d_order, p->order_batch.data(), ids.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           st),
+            "ifci_davidson upload");
+  }
+  SolveArgs A;
+  A.inc = p->d_inc;
+  A.order = p->d_order;
+  A.count = (int32_t)ids.size();
+  A.precision = p->opt.precision;
+  A.max_iter = p->opt.max_iter;
+  A.max_space = p->opt.max_space;
+  A.r_tol = p->opt.r_tol;
+  A.r_tol_inner = p->opt.r_tol_inner;
+  A.tables = p->d_tables;
+  A.ints = p->ws_ints();
+  A.dav = p->ws_dav();
+  A.first = first;
+  A.e_out = e_out;
+  A.status_out = status_out;
+  A.iters_out = iters_out;
+  A.resid_out = resid_out;
+  A.evict = evict_mask;
+  A.e_const = p->e_const;
+  A.phase = p->phase_counters;
+  HIP_TRY(launch_batched(A, batch_lds(p, ids), st), "ifci_davidson batched");
   return IFCI_OK;
 }
 
@@ -578,40 +694,12 @@ ifci_status ifci_davidson(ifci_plan_t p, int64_t first, int64_t count, double* e
       else
         rest.push_back(i);
     }
-  if (!ids.empty()) {
-    if (ids != p->order_batch) {
-      // a new work list: wait for any earlier upload from order_batch
-      // before reusing its host memory (a repeated list is already there)
-      HIP_TRY(hipStreamSynchronize(st), "ifci_davidson");
-      p->order_batch = ids;
-      HIP_TRY(hipMemcpyAsync(p->d_order, p->order_batch.data(), ids.size() * sizeof(int32_t),
-                             hipMemcpyHostToDevice, st),
-              "ifci_davidson upload");
-    }
-    SolveArgs A;
-    A.inc = p->d_inc;
-    A.order = p->d_order;
-    A.count = (int32_t)ids.size();
-    A.precision = p->opt.precision;
-    A.max_iter = p->opt.max_iter;
-    A.max_space = p->opt.max_space;
-    A.r_tol = p->opt.r_tol;
-    A.r_tol_inner = p->opt.r_tol_inner;
-    A.tables = p->d_tables;
-    A.ints = p->ws_ints();
-    A.dav = p->ws_dav();
-    A.first = first;
-    A.e_out = e_out;
-    A.status_out = status_out;
-    A.iters_out = iters_out;
-    A.resid_out = resid_out;
-    A.evict = evict_mask;
-    A.e_const = p->e_const;
-    A.phase = p->phase_counters;
-    HIP_TRY(launch_batched(A, batch_lds(p, ids), st), "ifci_davidson batched");
-  }
+  s = launch_on_chip(p, ids, first, e_out, status_out, evict_mask, iters_out, resid_out, st);
+  if (s != IFCI_OK) return s;
   if (!rest.empty() && !plain_only) {
-    s = run_wide(p, rest, first, e_out, status_out, iters_out, resid_out, evict_mask, st);
+    std::vector<WideMember> mem(1);
+    mem[0] = WideMember{p, rest, first, e_out, status_out, iters_out, resid_out, evict_mask};
+    s = run_wide(p, mem, st);
     if (s != IFCI_OK) return s;
   } else if (!rest.empty()) {
     std::vector<uint8_t> ev;
@@ -694,6 +782,58 @@ ifci_status ifci_davidson(ifci_plan_t p, int64_t first, int64_t count, double* e
     }
   }
   for (int64_t i = first; i < first + count; ++i) p->solved[i] = 1;
+  return IFCI_OK;
+}
+
+ifci_status ifci_davidson_group(const ifci_plan_t* plans, int32_t n_plans, double* const* e_out,
+                                int32_t* const* status_out, int32_t* const* iters_out, double* const* resid_out,
+                                ifci_stream_t stream) {
+  if (!plans || n_plans < 1 || !e_out || !status_out) {
+    set_error("ifci_davidson_group: null plans or outputs");
+    return IFCI_ERR_ARG;
+  }
+  ifci_plan_s* O = plans[0];
+  for (int32_t j = 0; j < n_plans; ++j) {
+    ifci_plan_s* p = plans[j];
+    if (check_plan(p) != IFCI_OK || !e_out[j] || !status_out[j]) {
+      set_error("ifci_davidson_group: null plan or output of plan " + std::to_string(j));
+      return IFCI_ERR_ARG;
+    }
+    if (p->device != O->device || p->opt.precision != O->opt.precision || p->opt.solver != IFCI_SOLVER_BATCHED ||
+        O->opt.solver != IFCI_SOLVER_BATCHED || p->opt.max_iter != O->opt.max_iter || p->opt.r_tol != O->opt.r_tol ||
+        p->opt.r_tol_inner != O->opt.r_tol_inner || p->opt.max_space != O->opt.max_space ||
+        p->opt.flags != O->opt.flags) {
+      set_error("ifci_davidson_group: plans must share the device and the options, with the batched solver");
+      return IFCI_ERR_ARG;
+    }
+    for (int32_t k = 0; k < j; ++k)
+      if (plans[k] == p) {
+        set_error("ifci_davidson_group: a plan is listed twice");
+        return IFCI_ERR_ARG;
+      }
+  }
+  for (int32_t j = 0; j < n_plans; ++j) {
+    ifci_status s = need_ints(plans[j]);
+    if (s != IFCI_OK) return s;
+  }
+  DeviceGuard g(O->device);
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<WideMember> mem;
+  for (int32_t j = 0; j < n_plans; ++j) {
+    ifci_plan_s* p = plans[j];
+    std::vector<int32_t> ids, rest;
+    for (int32_t i : p->order_all) (p->batched_ok[i] ? ids : rest).push_back(i);
+    int32_t* it = iters_out ? iters_out[j] : nullptr;
+    double* rs = resid_out ? resid_out[j] : nullptr;
+    ifci_status s = launch_on_chip(p, ids, 0, e_out[j], status_out[j], nullptr, it, rs, st);
+    if (s != IFCI_OK) return s;
+    if (!rest.empty()) mem.push_back(WideMember{p, rest, 0, e_out[j], status_out[j], it, rs, nullptr});
+  }
+  if (!mem.empty()) {
+    ifci_status s = run_wide(O, mem, st);
+    if (s != IFCI_OK) return s;
+  }
+  for (int32_t j = 0; j < n_plans; ++j) std::fill(plans[j]->solved.begin(), plans[j]->solved.end(), 1);
   return IFCI_OK;
 }
 

@@ -55,6 +55,8 @@ struct ifci_plan_s {
     std::vector<std::vector<char>> host;
   };
   std::vector<InFlight> in_flight;
+  char* group_ctl = nullptr;  // control block of solves across several plans (grown on demand)
+  int64_t group_ctl_bytes = 0;
   // device
   ifci::IncDev* d_inc = nullptr;
   int32_t* d_orbs = nullptr;

@@ -63,6 +63,10 @@ _SIGNATURES = {
     "ifci_davidson": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p]),
+    "ifci_davidson_group": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.c_void_p]),
     "ifci_vector": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
     "ifci_energy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
@@ -283,6 +287,23 @@ class Plan:
             w = torch.as_tensor(weights, dtype=torch.float64, device=dev).contiguous()
         _check(lib().ifci_rdm(self._h, _ptr(w), _ptr(dh), _ptr(dg), _stream(stream)))
         return dh, dg
+
+
+def davidson_group(plans, stream=None):
+    """ifci_davidson_group over attached plans: one batched solve of every
+    increment of every plan.  Returns [(E, status, iters, resid)] per plan."""
+    import torch
+    outs = []
+    for pl in plans:
+        dev = torch.device("cuda", pl.device)
+        n = pl.n_inc
+        outs.append((torch.empty(n, dtype=torch.float64, device=dev), torch.empty(n, dtype=torch.int32, device=dev),
+                     torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.float64, device=dev)))
+    arr = lambda xs: (ctypes.c_void_p * len(xs))(*[ctypes.c_void_p(x.data_ptr()) for x in xs])
+    handles = (ctypes.c_void_p * len(plans))(*[pl._h.value for pl in plans])
+    _check(lib().ifci_davidson_group(handles, len(plans), arr([o[0] for o in outs]), arr([o[1] for o in outs]),
+                                     arr([o[2] for o in outs]), arr([o[3] for o in outs]), _stream(stream)))
+    return outs
 
 
 def solve(problem, precision=FP64, solver=BATCHED, device: int = 0, **opts):

@@ -27,7 +27,7 @@ def test_exports_every_declared_symbol(L):
     assert len(names) >= 15
     for n in sorted(names):
         assert hasattr(L, n), n
-    assert L.ifci_abi_version() == 1
+    assert L.ifci_abi_version() == 2
 
 
 @pytest.mark.parametrize("k,n", [(k, n) for k in range(1, 13) for n in range(0, k + 1)])
@@ -116,3 +116,22 @@ def test_bad_options_and_state_errors(L):
     assert L.ifci_davidson(h, 0, 99, ctypes.c_void_p(256), ctypes.c_void_p(512), None, None, None, None) == 1
     assert L.ifci_plan_destroy(h) == 0
     assert L.ifci_status_string(5) == b"not converged"
+
+
+def test_davidson_group_argument_errors(L):
+    """ifci_davidson_group refuses null plans, mismatched options and plans
+    without workspace before any device work."""
+    import ctypes
+    from paper_2307_10675_amd import ifci, synthetic
+    p = synthetic.single(4, 12, 1)
+    a = ifci.Plan(p)
+    b = ifci.Plan(p, precision=ifci.MIXED)
+    null = (ctypes.c_void_p * 1)(None)
+    assert L.ifci_davidson_group(None, 1, null, null, None, None, None) == 1
+    two = (ctypes.c_void_p * 2)(a._h.value, b._h.value)
+    outs = (ctypes.c_void_p * 2)(1, 1)
+    assert L.ifci_davidson_group(two, 2, outs, outs, None, None, None) == 1   # options differ
+    same = (ctypes.c_void_p * 2)(a._h.value, a._h.value)
+    assert L.ifci_davidson_group(same, 2, outs, outs, None, None, None) == 1  # listed twice
+    one = (ctypes.c_void_p * 1)(a._h.value)
+    assert L.ifci_davidson_group(one, 1, outs, outs, None, None, None) == 6   # no workspace
