@@ -185,6 +185,21 @@ ifci_status ifci_set_integrals(ifci_plan_t plan, const double* h, const double* 
 ifci_status ifci_sigma(ifci_plan_t plan, int64_t inc, const double* c, double* sigma,
                        int32_t precision, ifci_stream_t stream);
 
+/* ifci_sigma for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same product, arguments, layout and errors as ifci_sigma, but the
+ * product's scratch (E, npair x n_det values of the contraction precision)
+ * lives in a fixed array of 32 MiB that the library holds on every device
+ * it runs on until the process ends, instead of in the plan's workspace.
+ * The call allocates nothing (the plan, its workspace and integrals are set
+ * up beforehand).  Increments whose E exceeds 32 MiB (in FP64: 10o10e fits,
+ * 12o12e does not) return IFCI_ERR_UNSUPPORTED.  Every call on one device
+ * shares that device's array, which keeps the last call's contents (each
+ * call overwrites all it reads): calls that overlap on one device -- on
+ * different streams, or from different threads -- race. */
+ifci_status ifci_sigma_noalloc(ifci_plan_t plan, int64_t inc, const double* c, double* sigma,
+                               int32_t precision, ifci_stream_t stream);
+
 /* Same product restricted to symmetric c (C = C^T, the sector the solvers
  * search): c and sigma are packed scaled vectors (entry (a <= b) at
  * b (b + 1) / 2 + a, off-diagonal entries times sqrt 2), n_str (n_str + 1) / 2

@@ -134,6 +134,13 @@ ifci_status ensure_device(ifci_plan_s* P) {
     free_device(P);
     return dev_err(e, "uploading plan tables");
   }
+  // the static scratch array's address on this device, for the
+  // allocation-free entry point
+  e = static_scratch(nullptr);
+  if (e != hipSuccess) {
+    free_device(P);
+    return dev_err(e, "static scratch address");
+  }
   P->on_device = true;
   return IFCI_OK;
 }
@@ -638,6 +645,33 @@ ifci_status ifci_sigma(ifci_plan_t p, int64_t inc, const double* c, double* sigm
   HIP_TRY(launch_sigma_wide(d, p->d_inc, (int)inc, p->ws_ints(), p->d_tables, c, sigma, p->ws_E(), precision, 0,
                             0.0, (hipStream_t)stream),
           "ifci_sigma");
+  return IFCI_OK;
+}
+
+ifci_status ifci_sigma_noalloc(ifci_plan_t p, int64_t inc, const double* c, double* sigma, int32_t precision,
+                               ifci_stream_t stream) {
+  if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
+  if (inc < 0 || inc >= (int64_t)p->inc.size() || !c || !sigma || c == sigma ||
+      (precision != IFCI_FP64 && precision != IFCI_MIXED)) {
+    set_error("ifci_sigma_noalloc: bad increment, pointer or precision");
+    return IFCI_ERR_ARG;
+  }
+  ifci_status s = need_ints(p);
+  if (s != IFCI_OK) return s;
+  const IncDev& d = p->inc[inc];
+  const int64_t need = d.npair * d.n_det * (precision == IFCI_MIXED ? 4 : 8);
+  if (need > kStaticScratchDoubles * 8) {
+    set_error("ifci_sigma_noalloc: this increment's product needs " + std::to_string(need) +
+              " bytes of scratch; the static scratch holds " + std::to_string(kStaticScratchDoubles * 8) +
+              " (use ifci_sigma)");
+    return IFCI_ERR_UNSUPPORTED;
+  }
+  DeviceGuard g(p->device);
+  double* E = nullptr;
+  HIP_TRY(static_scratch(&E), "ifci_sigma_noalloc");
+  HIP_TRY(launch_sigma_wide(d, p->d_inc, (int)inc, p->ws_ints(), p->d_tables, c, sigma, E, precision, 0, 0.0,
+                            (hipStream_t)stream),
+          "ifci_sigma_noalloc");
   return IFCI_OK;
 }
 

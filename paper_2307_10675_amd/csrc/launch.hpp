@@ -32,6 +32,10 @@ hipError_t launch_sigma_one(const IncDev* incs, int inc, const double* ints, con
 bool sigma_column_supported(const IncDev& d);
 hipError_t prepare_sigma_wide();  // one-time kernel attributes, thread safe
 int64_t sigma_column_ws_doubles(const IncDev& d);  // workspace of the column path
+// The static scratch array (plain.hip): its device address on the current
+// device (looked up once per device), kStaticScratchDoubles doubles.
+constexpr int64_t kStaticScratchDoubles = (int64_t)4 << 20;  // 32 MiB
+hipError_t static_scratch(double** out);
 hipError_t launch_sigma_wide(const IncDev& d, const IncDev* d_inc_dev, int inc, const double* ints,
                              const int32_t* tables, const double* c, double* sig, double* E,
                              int precision, int mode, double shift, hipStream_t st);

@@ -4,6 +4,7 @@
 // the unfused per-increment path (one launch per step, the host reading the
 // solver state every iteration) that the batched solvers are compared with.
 // The kernel bodies live in sigma_wide.hpp and davidson_ops.hpp.
+#include <map>
 #include <mutex>
 #include <set>
 #include <utility>
@@ -122,6 +123,33 @@ static hipError_t launch_sigma_column(const IncDev& d, const double* V, const in
                         : launch_column_split<double, 16>(d, V, ptab, ptabT, c, sig, ws, shift, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+// ---------------------------------------------------------------- static scratch
+// E of the general product for callers that cannot allocate
+// (ifci_sigma_noalloc): a fixed array of kStaticScratchDoubles doubles on
+// every device the library runs on, held until the process ends.  Host code
+// never uses the array's name as an address: it uses the device address
+// hipGetSymbolAddress gives for the current device, looked up once per
+// device.  Every call on a device shares that device's array.
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+hipError_t static_scratch(double** out) {
+  static std::mutex mu;
+  static std::map<int, double*> addr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    double* p = nullptr;
+    e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    it = addr.emplace(dev, p).first;
+  }
+  if (out) *out = it->second;
+  return hipSuccess;
 }
 
 hipError_t launch_sigma_wide(const IncDev& d, const IncDev*, int, const double* ints, const int32_t* tables,

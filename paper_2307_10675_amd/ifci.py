@@ -60,6 +60,8 @@ _SIGNATURES = {
                                   ctypes.c_int32, ctypes.c_void_p]),
     "ifci_sigma_sector": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_int32, ctypes.c_void_p]),
+    "ifci_sigma_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_int32, ctypes.c_void_p]),
     "ifci_davidson": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p]),
@@ -220,6 +222,11 @@ class Plan:
         c = c.contiguous()
         out = torch.empty_like(c)
         _check(lib().ifci_sigma(self._h, inc, _ptr(c), _ptr(out), precision, _stream(stream)))
+        return out
+
+    def sigma_noalloc(self, inc: int, out, c, precision=FP64, stream=None):
+        """ifci_sigma_noalloc into the caller's `out` (nothing is allocated)."""
+        _check(lib().ifci_sigma_noalloc(self._h, inc, _ptr(c), _ptr(out), precision, _stream(stream)))
         return out
 
     def sigma_sector(self, inc: int, c, precision=FP64, stream=None):
