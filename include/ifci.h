@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define IFCI_ABI_VERSION 2
+#define IFCI_ABI_VERSION 3
 
 typedef struct ifci_plan_s* ifci_plan_t;
 typedef void* ifci_stream_t; /* a hipStream_t; NULL = the null stream */
@@ -105,6 +105,16 @@ typedef struct {
                          three-vector {x, w, p} iteration (locally
                          optimal, no restarts) */
   uint32_t flags;     /* IFCI_FLAG_* bits */
+  int32_t n_guess;    /* three-vector on-chip solver (max_space 3): the
+                         n_guess (at most 64, rounded down to even) lowest
+                         diagonal entries of the symmetric sector span a
+                         block of H that is diagonalised once per
+                         increment; its lowest eigenvector is the initial
+                         guess and its exact inverse the preconditioner on
+                         those entries (a block Davidson preconditioner).
+                         0 or 1: the single lowest determinant and the
+                         diagonal preconditioner.  The other solvers use
+                         the latter in any case. */
 } ifci_options;
 
 /* ifci_davidson returns as soon as the work of every increment is
@@ -118,7 +128,7 @@ typedef struct {
 int ifci_abi_version(void);
 
 /* Fill *opt with the defaults: FP64, batched, r_tol 1e-7, r_tol_inner 1e-4,
- * max_iter 300, max_space 12. */
+ * max_iter 300, max_space 12, flags 0, n_guess 64. */
 void ifci_default_options(ifci_options* opt);
 
 /* Validate the problem, enumerate the increments, build the string and

@@ -411,6 +411,7 @@ ifci_status launch_on_chip(ifci_plan_s* p, const std::vector<int32_t>& ids, int6
   A.precision = p->opt.precision;
   A.max_iter = p->opt.max_iter;
   A.max_space = p->opt.max_space;
+  A.n_guess = p->opt.n_guess;
   A.r_tol = p->opt.r_tol;
   A.r_tol_inner = p->opt.r_tol_inner;
   A.tables = p->d_tables;
@@ -444,6 +445,7 @@ void ifci_default_options(ifci_options* o) {
   o->max_iter = 300;
   o->max_space = 12;
   o->flags = 0;
+  o->n_guess = 64;
 }
 
 const char* ifci_status_string(ifci_status s) {

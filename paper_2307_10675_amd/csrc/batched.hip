@@ -45,6 +45,7 @@
 
 #include "device_common.hpp"
 #include "launch.hpp"
+#include "pspace.hpp"
 
 namespace ifci {
 
@@ -64,6 +65,10 @@ struct Lds {
   double* G;       // [16*16] subspace matrix
   double* Qp;      // [16*16] eigenvectors of the previous subspace matrix
   double* Lam;     // [16] its eigenvalues
+  int* pidx;       // [kPsMax] packed entries of the P-space block (three-vector solver)
+  double* plam;    // [kPsMax + 2] eigenvalues of that block, minus E0; [kPsMax]: the
+                   // largest diagonal entry of the block (with pidx[P - 1] it bounds
+                   // the block in (H_II, I) order)
   double* cp;      // CI vector, full (n+1) x (n+1) of T with a zero last row and column
   double* sp;      // [n_sym] sigma accumulator, packed scaled
   // transient (overlaid by the E slices during sigma)
@@ -103,7 +108,8 @@ __host__ __device__ inline int64_t colb_bytes(int n_str) {
 __host__ __device__ inline int64_t persistent_bytes(int k, int n_str, int n_link) {
   const int64_t ns = tri(n_str);
   return colb_bytes(n_str) + ptab_bytes(k, n_str) + a16(4 * (int64_t)n_str * n_link) + a16(4 * n_str) +
-         a16(8 * n_str) + a16(8 * (2 * k * k + k)) + 8 * (256 + 256 + 16) + cp_bytes(n_str) + a16(8 * ns);
+         a16(8 * n_str) + a16(8 * (2 * k * k + k)) + 8 * (256 + 256 + 16) + 12 * kPsMax + 16 + cp_bytes(n_str) +
+         a16(8 * ns);
 }
 __host__ __device__ inline int64_t transient_bytes(int n_str) {
   return a16(8 * tri(n_str)) + 8 * (256 + 256 + 16 + 16 + 16) + 4 * 16 + 8 * 32 + 4 * 16 + 16 + 8 * 16 * 24;
@@ -167,6 +173,10 @@ __device__ inline Lds carve(char* base, const IncDev& d, int lds_bytes) {
   p += 8 * 256;
   L.Lam = (double*)p;
   p += 8 * 16;
+  L.plam = (double*)p;
+  p += 8 * (kPsMax + 2);
+  L.pidx = (int*)p;
+  p += 4 * kPsMax;
   L.cp = (double*)p;
   p += cp_bytes(n);
   L.sp = (double*)p;
@@ -1107,6 +1117,232 @@ __device__ inline void small_eig3(const double g[3][3], double* theta, double z[
   *theta = z[0] * gz[0] + z[1] * gz[1] + z[2] * gz[2];
 }
 
+// ---------------------------------------------------------------------------
+// P-space block of the three-vector solver (pspace.hpp): size, set-up, and
+// the per-iteration correction.
+
+// Byte offset from L.et of the P-space scratch: past the transient arrays.
+__device__ inline int64_t ps_scratch_offset(const IncDev& d) { return a16(transient_bytes(d.n_str)); }
+
+// P-space scratch from L.et + ps_scratch_offset: U [P][P] FP32 (where the
+// FP32 image is kept during iterations), A [P][P] FP32, the Jacobi
+// rotations (2 P floats) and planes (P ints) in 1 KB, h' [K][K] and a copy
+// of the pair matrix V [np][np] and k [K][K] of the increment (FP64) for
+// the Slater-Condon elements.
+__device__ inline int64_t ps_scratch_bytes(int P, int K) {
+  const int64_t np = K * (K + 1) / 2;
+  return 8LL * P * P + 1024 + 8LL * (2 * K * K + np * np) + 64;
+}
+
+// Block size for this increment: even, at most n_guess, kPsMax and the
+// sector dimension, with room in LDS for the set-up (A, U, h', the
+// rotations) and, across iterations, for the FP32 U image below the
+// diagonal-pair weights of both precisions.
+template <int K>
+__device__ inline int ps_size(const IncDev& d, const Lds& L, int n_guess) {
+  int P = n_guess < kPsMax ? n_guess : kPsMax;
+  if (P > (int)d.n_sym) P = (int)d.n_sym;
+  P &= ~1;
+  const int64_t off = ps_scratch_offset(d);
+  const int64_t wt = wt_offset(L, K, 4) < wt_offset(L, K, 8) ? wt_offset(L, K, 4) : wt_offset(L, K, 8);
+  while (P >= 2 && (off + ps_scratch_bytes(P, K) > L.et_total || off + 4LL * P * P > wt)) P -= 2;
+  return P >= 2 ? P : 0;
+}
+
+// Block position of this thread's entry e, packed 7 bits per entry in a
+// 64-bit word (0x7f: not in the block): kept compact because it stays live
+// across every sigma.
+__device__ __forceinline__ int ps_pos(uint64_t pk, int e) { return (int)((pk >> (7 * e)) & 0x7f); }
+
+// First half of the set-up: the P lowest diagonal entries (ties to the
+// lower index) in L.pidx, the largest of their diagonal values in
+// L.plam[kPsMax], their block positions for this thread's entries in pk
+// (ps_pos), and H_PP - E0 from the Slater-Condon rules in the scratch
+// matrix A.  An entry I is in the block exactly when (H_II, I) <=
+// (L.plam[kPsMax], L.pidx[P - 1]) in lexicographic order.
+template <int K, int NE>
+__device__ __forceinline__ void ps_build(const IncDev& d, const Lds& L, const double* __restrict__ B,
+                                                   const double* HD, double E0, int P, uint64_t& pk, int& parity) {
+  static_assert(NE <= 9, "seven bits per entry in 64");
+  const int tid = threadIdx.x, nsi = (int)d.n_sym;
+  const int lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const IntBlock ib = int_block(K);
+  double hv[NE];
+  unsigned avail = 0;
+  pk = ~0ull;
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    const int i = tid + e * kBatchThreads;
+    hv[e] = 1e300;
+    if (i < nsi) {
+      hv[e] = HD[i];
+      avail |= 1u << e;
+    }
+  }
+  // selection: P rounds of a block argmin over the entries not yet taken
+  for (int j = 0; j < P; ++j) {
+    double best = 1e300;
+    int bi = 0x7fffffff;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int i = tid + e * kBatchThreads;
+      if ((avail >> e & 1u) && (hv[e] < best || (hv[e] == best && i < bi))) best = hv[e], bi = i;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ov < best || (ov == best && oi < bi)) best = ov, bi = oi;
+    }
+    double* buf = L.red + parity * 128;
+    parity ^= 1;
+    if (lane == 0) {
+      buf[2 * wave] = best;
+      buf[2 * wave + 1] = (double)bi;
+    }
+    __syncthreads();
+    double wb = buf[0];
+    int wi = (int)buf[1];
+    for (int w = 1; w < nw; ++w) {
+      const double v = buf[2 * w];
+      const int ix = (int)buf[2 * w + 1];
+      if (v < wb || (v == wb && ix < wi)) wb = v, wi = ix;
+    }
+    if ((wi & (kBatchThreads - 1)) == tid) {
+      const int e = wi / kBatchThreads;
+#pragma unroll
+      for (int q = 0; q < NE; ++q)
+        if (q == e) {
+          avail &= ~(1u << q);
+          pk = (pk & ~(0x7full << (7 * q))) | ((uint64_t)j << (7 * q));
+        }
+    }
+    if (tid == 0) {
+      L.pidx[j] = wi;
+      L.plam[kPsMax] = wb;
+    }
+  }
+  float* Am = (float*)(L.et + ps_scratch_offset(d)) + P * P;
+  double* hp = (double*)(Am + P * P + 256);
+  double* kl = hp + K * K;
+  double* Vl = kl + K * K;
+  constexpr int NP = K * (K + 1) / 2;
+  for (int t = tid; t < NP * NP; t += blockDim.x) Vl[t] = B[ib.V + t];
+  for (int t = tid; t < K * K; t += blockDim.x) kl[t] = B[ib.keff + t];
+  __syncthreads();
+  ActInts I;
+  I.V = Vl;
+  I.keff = kl;
+  I.hp = hp;
+  I.Jm = L.Jm;
+  I.Km = L.Km;
+  I.k = K;
+  I.np = K * (K + 1) / 2;
+  I.inv_nel = d.na > 0 ? 1.0 / (2.0 * d.na) : 0.0;
+  // h'_pq = k_pq + 1/2 sum_r (pr|rq)
+  for (int t = tid; t < K * K; t += blockDim.x) {
+    const int p = t / K, q = t - p * K;
+    double v = I.keff[t];
+    for (int r = 0; r < K; ++r) v += 0.5 * aeri(I, p, r, r, q);
+    hp[t] = v;
+  }
+  __syncthreads();
+  for (int t = tid; t < P * P; t += blockDim.x) {
+    const int r = t / P, c = t - r * P;
+    if (c < r) continue;
+    double v = sector_element(I, L.strs, L.F, L.pidx[r], L.pidx[c]);
+    if (r == c) v -= E0;
+    Am[r * P + c] = (float)v;
+    Am[c * P + r] = (float)v;
+  }
+  __syncthreads();
+}
+
+// Second half: the eigenpairs of A in FP32 (eigenvalues in L.plam, U
+// [l][j] in the scratch and in Ug) and the lowest eigenvector as the
+// initial vector in x (global) and L.tv.  FP32 holds the eigenvalues of
+// the shifted block to about 1e-7 of its norm: ample for a preconditioner
+// and a starting vector, neither of which sets the converged energy.
+template <int K, int NE>
+__device__ __forceinline__ void ps_eigen(const IncDev& d, const Lds& L, int P, uint64_t pk, float* Ug, double* xv,
+                                         int& parity) {
+  const int tid = threadIdx.x, nsi = (int)d.n_sym;
+  float* Um = (float*)(L.et + ps_scratch_offset(d));
+  float* Am = Um + P * P;
+  float* cs = Am + P * P;
+  int* pq = (int*)(cs + 2 * kPsMax);
+  // squared off-diagonal part 1e-5 of the squared norm (an off-diagonal
+  // part near 0.3% of the matrix): iteration counts of the solver were
+  // found unchanged against an exact eigen-decomposition
+  block_jacobi(Am, Um, P, cs, pq, L.red, parity, 1e-5);
+  // eigenvalues and the lowest one (ties to the lower index)
+  for (int j = tid; j < P; j += blockDim.x) L.plam[j] = (double)Am[j * P + j];
+  int j0 = 0;
+  float l0 = Am[0];
+  for (int j = 1; j < P; ++j)
+    if (Am[j * P + j] < l0) l0 = Am[j * P + j], j0 = j;
+  for (int t = tid; t < P * P / 4; t += blockDim.x) ((float4*)Ug)[t] = ((const float4*)Um)[t];
+  // the initial vector: column j0 of U on the block's entries, normalised
+  // in FP64
+  double acc[1] = {0.0};
+  double xe[NE];
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    const int j = ps_pos(pk, e);
+    xe[e] = j != 0x7f ? (double)Um[j * P + j0] : 0.0;
+    acc[0] += xe[e] * xe[e];
+  }
+  block_sum_1b<1>(acc, L.red, parity);
+  const double inv = 1.0 / sqrt(acc[0]);
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    const int i = tid + e * kBatchThreads;
+    if (i < nsi) {
+      xv[i] = xe[e] * inv;
+      L.tv[i] = xe[e] * inv;
+    }
+  }
+  __syncthreads();
+}
+
+// t_P = U diag(1 / (theta - lam)) U^T r_P with U the FP32 image in LDS (Us,
+// [l][j]), r_P gathered from the full residual in v (LDS, every entry
+// written by its owner before the call) and t_P scattered back into v over
+// the block's entries; zP: LDS [kPsMax] doubles.  Each wave handles eight
+// rows (eight lanes per row, eight terms each, summed by a fixed
+// butterfly).  Three barriers.
+__device__ inline void ps_apply(const float* Us, int P, double theta, const double* plam, const int* pidx,
+                                double* v, double* zP) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int row = wave * 8 + (lane >> 3), part = lane & 7;
+  __syncthreads();
+  {
+    // z_j = (sum_l U[l][j] r_l) / (theta - lam_j)
+    double y = 0.0;
+    if (row < P)
+      for (int l = part * 8; l < part * 8 + 8 && l < P; ++l) y += (double)Us[l * P + row] * v[pidx[l]];
+    y += __shfl_xor(y, 1, 64);
+    y += __shfl_xor(y, 2, 64);
+    y += __shfl_xor(y, 4, 64);
+    if (row < P && part == 0) {
+      double den = theta - plam[row];
+      if (fabs(den) < 1e-8) den = (den < 0.0) ? -1e-8 : 1e-8;
+      zP[row] = y / den;
+    }
+  }
+  __syncthreads();
+  {
+    // t_l = sum_j U[l][j] z_j
+    double t = 0.0;
+    if (row < P)
+      for (int j = part * 8; j < part * 8 + 8 && j < P; ++j) t += (double)Us[row * P + j] * zP[j];
+    t += __shfl_xor(t, 1, 64);
+    t += __shfl_xor(t, 2, 64);
+    t += __shfl_xor(t, 4, 64);
+    if (row < P && part == 0) v[pidx[row]] = t;
+  }
+  __syncthreads();
+}
+
 // Locally optimal block-free iteration (Davidson restarted every step to the
 // three vectors {x, w, p}: the Ritz vector, its preconditioned residual and
 // the previous search direction; LOBPCG with block size one).  The basis is
@@ -1150,16 +1386,31 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
   argmin_block(HD, ns, L);
   const double E0 = L.scal[0];
   const int64_t guess = L.iscal[0];
-  for (int64_t i = tid; i < ns; i += blockDim.x) {
-    const double v = (i == guess) ? 1.0 : 0.0;
-    L.tv[i] = v;
-    xv[i] = v;
-  }
-  __syncthreads();
-  IFCI_MARK(kPhPrologue);
-
   // vector entries per thread: the packed sector of the largest K-orbital shape
   constexpr int NE = (max_strings(K) * (max_strings(K) + 1) / 2 + kBatchThreads - 1) / kBatchThreads;
+  int bsp = 0;  // buffer parity of block_sum_1b
+  // P-space block: initial vector and block preconditioner (or the lowest
+  // determinant and the diagonal preconditioner)
+  float* Ug = (float*)(base + ps_image_offset(st, mmax));
+  const int P = A.n_guess > 1 ? ps_size<K>(d, L, A.n_guess) : 0;
+  float* Us = (float*)(L.et + ps_scratch_offset(d));
+  double* zP = L.Gs;
+  if (P > 0) {
+    uint64_t pk;  // block positions of this thread's entries (ps_pos)
+    ps_build<K, NE>(d, L, B, HD, E0, P, pk, bsp);
+    IFCI_MARK(kPhPrologue);
+    ps_eigen<K, NE>(d, L, P, pk, Ug, xv, bsp);
+    IFCI_MARK(kPhRestart);
+  } else {
+    for (int64_t i = tid; i < ns; i += blockDim.x) {
+      const double v = (i == guess) ? 1.0 : 0.0;
+      L.tv[i] = v;
+      xv[i] = v;
+    }
+    __syncthreads();
+  }
+  IFCI_MARK(kPhPrologue);
+
   // every vector of the increment addressed from `base` by a 32-bit offset
   const int nsi = (int)ns, sti = (int)st, mst = mmax * (int)st;
   const int ew64 = et_waves_for<double, K>(d, L);
@@ -1169,7 +1420,6 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
   double theta = 0.0, resid = 1e300;
   const int64_t o = (int64_t)id - A.first;
   const bool evict = A.evict && A.evict[o] != 0;
-  int bsp = 0;           // buffer parity of block_sum_1b
   bool staged = false;   // cp / sp already hold the next sigma's input
   bool fresh = true;     // x has no sigma yet (start or precision switch)
   bool have_p = false;
@@ -1212,6 +1462,10 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
     }
     __syncthreads();
     IFCI_MARK(kPhSigma);
+    // the FP32 eigenvectors of the P-space block back into LDS (the E slices
+    // of every sigma overwrite them); read before the correction needs them
+    if (P > 0)
+      for (int u = tix; u < P * P / 4; u += kBatchThreads) ((float4*)Us)[u] = ((const float4*)Ug)[u];
 #pragma unroll
     for (int e = 0; e < NE; ++e) rs[e] = L.sp[min(tix + e * kBatchThreads, nsi - 1)];
 #pragma unroll
@@ -1295,7 +1549,8 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
       pap = npap;
     }
     // ---- update x, Ax, p, Ap in registers; residual r = Ax - theta x and
-    // correction t = r / (theta - (H_II - E0)) with its overlaps
+    // correction t = r / (theta - (H_II - E0)) -- on the P-space entries the
+    // block's exact inverse -- with its overlaps
     double rt[NE];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -1316,13 +1571,24 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
       }
       const bool in = tid + e * kBatchThreads < nsi;
       const double r = in ? sx - theta * x : 0.0;
+      rt[e] = r;
+      acc[0] += r * r;
+      if (P > 0 && in) L.tv[tix + e * kBatchThreads] = r;
+    }
+    // the block's entries: (H_II, I) up to its last one
+    const double ps_h = P > 0 ? L.plam[kPsMax] : -1e300;
+    const int ps_i = P > 0 ? L.pidx[P - 1] : -1;
+    if (P > 0) ps_apply(Us, P, theta, L.plam, L.pidx, L.tv, zP);
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int i = tix + e * kBatchThreads;
       double den = theta - (rhd[e] - E0);
       if (fabs(den) < 1e-8) den = (den < 0.0) ? -1e-8 : 1e-8;
-      const double t = r / den;
+      const bool in_p = i < nsi && (rhd[e] < ps_h || (rhd[e] == ps_h && i <= ps_i));
+      const double t = in_p ? L.tv[i] : rt[e] / den;
       rt[e] = t;
-      acc[0] += r * r;
       acc[1] += t * t;
-      acc[2] += x * t;
+      acc[2] += rx[e] * t;
       acc[3] += (new_p ? rp[e] : 0.0) * t;
     }
     block_sum_1b<4>(acc, L.red, bsp);

@@ -59,9 +59,16 @@ __host__ __device__ inline IntBlock int_block(int k) {
   return b;
 }
 
+// Largest P-space block of the on-chip three-vector solver.
+constexpr int kPsMax = 64;
+
 // Davidson storage of one increment (doubles from vec_off): basis V[mmax],
-// sigma S[mmax], diagonal, converged vector X; each `stride` long.
+// sigma S[mmax], diagonal, converged vector X, each `stride` long; then the
+// FP32 eigenvector image of the P-space block (kPsMax^2 floats).
 __host__ __device__ inline int64_t vec_block_size(int64_t stride, int mmax) {
+  return (2 * (int64_t)mmax + 2) * stride + kPsMax * kPsMax / 2;
+}
+__host__ __device__ inline int64_t ps_image_offset(int64_t stride, int mmax) {
   return (2 * (int64_t)mmax + 2) * stride;
 }
 
@@ -72,6 +79,7 @@ struct SolveArgs {
   int32_t precision;
   int32_t max_iter;
   int32_t max_space;
+  int32_t n_guess;        // P-space block of the three-vector solver (0 or 1: none)
   double r_tol;
   double r_tol_inner;
   const int32_t* tables;

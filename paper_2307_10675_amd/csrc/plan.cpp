@@ -178,8 +178,10 @@ ifci_status plan_build(ifci_plan_s* P, const ifci_problem* pr, const ifci_option
   P->opt = *op;
   if (op->max_space < 2 || op->max_space > kMaxSpace || op->max_iter < 1 || !(op->r_tol > 0) ||
       (op->precision != IFCI_FP64 && op->precision != IFCI_MIXED) ||
-      (op->solver != IFCI_SOLVER_BATCHED && op->solver != IFCI_SOLVER_PLAIN)) {
-    set_error("invalid options (max_space 2..16, max_iter >= 1, r_tol > 0, precision, solver)");
+      (op->solver != IFCI_SOLVER_BATCHED && op->solver != IFCI_SOLVER_PLAIN) || op->n_guess < 0 ||
+      op->n_guess > kPsMax || (op->flags & ~(uint32_t)IFCI_FLAG_ASYNC_WIDE) != 0) {
+    set_error("invalid options (max_space 2..16, max_iter >= 1, r_tol > 0, precision, solver, n_guess 0..64, "
+              "flags)");
     return IFCI_ERR_ARG;
   }
   if (pr->body_ptr[0] != 0) {

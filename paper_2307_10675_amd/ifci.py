@@ -35,7 +35,7 @@ class Problem(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("solver", ctypes.c_int32), ("r_tol", ctypes.c_double),
                 ("r_tol_inner", ctypes.c_double), ("max_iter", ctypes.c_int32), ("max_space", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("n_guess", ctypes.c_int32)]
 
 
 _lib = None

@@ -27,7 +27,7 @@ def test_exports_every_declared_symbol(L):
     assert len(names) >= 15
     for n in sorted(names):
         assert hasattr(L, n), n
-    assert L.ifci_abi_version() == 2
+    assert L.ifci_abi_version() == 3
 
 
 @pytest.mark.parametrize("k,n", [(k, n) for k in range(1, 13) for n in range(0, k + 1)])

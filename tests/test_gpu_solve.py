@@ -12,8 +12,13 @@ from tests.helpers import active_hamiltonian, load_golden
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-9
-# max_space 12: thick-restart Davidson; max_space 3: the {x, w, p} solver
-SPACES = [12, 3]
+# max_space 12: thick-restart Davidson; max_space 3: the {x, w, p} solver,
+# started from the lowest determinant with the diagonal preconditioner
+# (n_guess 0) or from the lowest eigenvector of the 64-determinant P-space
+# block with that block's exact inverse as preconditioner (the default)
+SPACES = [pytest.param(dict(max_space=12), id="davidson12"),
+          pytest.param(dict(max_space=3, n_guess=0), id="3vec"),
+          pytest.param(dict(max_space=3), id="3vec_pspace")]
 
 
 def _check_sha(problem, g):
@@ -28,23 +33,25 @@ def test_workload0_fp64_davidson(rep, space):
     p = synthetic.workload(0, rep)
     g = load_golden(f"w0_r{rep}")
     _check_sha(p, g)
-    print(f"[solve] workload 0 replicate {rep} max_space {space}", flush=True)
-    plan, res = ifci.solve(p, r_tol=1e-10, max_space=space, max_iter=500)
+    print(f"[solve] workload 0 replicate {rep} {space}", flush=True)
+    plan, res = ifci.solve(p, r_tol=1e-10, **space, max_iter=500)
     torch.cuda.synchronize()
     assert int(res["status"][0]) == ifci.INC_DONE
     assert float(res["resid"][0]) <= 1e-10
     assert abs(float(res["E"][0]) - g["increments"][0]["E"]) <= TOL64
 
 
-@pytest.mark.parametrize("solver,space", [(ifci.BATCHED, 12), (ifci.BATCHED, 3), (ifci.PLAIN, 12)])
+@pytest.mark.parametrize("solver,space", [(ifci.BATCHED, dict(max_space=12)), (ifci.BATCHED, dict(max_space=3)),
+                                          (ifci.BATCHED, dict(max_space=3, n_guess=0)),
+                                          (ifci.PLAIN, dict(max_space=12))])
 def test_workload1_all_increments(solver, space):
     """10 bodies, order 3: all 175 increments, eps_S and the total."""
     import torch
     p = synthetic.workload(1)
     g = load_golden("w1")
     _check_sha(p, g)
-    print(f"[solve] workload 1 solver {solver} max_space {space}", flush=True)
-    plan, res = ifci.solve(p, solver=solver, r_tol=1e-8, max_space=space, max_iter=500)
+    print(f"[solve] workload 1 solver {solver} {space}", flush=True)
+    plan, res = ifci.solve(p, solver=solver, r_tol=1e-8, **space, max_iter=500)
     torch.cuda.synchronize()
     E = res["E"].cpu().numpy()
     st = res["status"].cpu().numpy()
@@ -68,7 +75,7 @@ def test_full_order_identity(space):
     p = synthetic.chain(4, seed=1100, order=4)
     g = load_golden("chain4_full")
     _check_sha(p, g)
-    plan, res = ifci.solve(p, r_tol=1e-9, max_space=space, max_iter=500)
+    plan, res = ifci.solve(p, r_tol=1e-9, **space, max_iter=500)
     torch.cuda.synchronize()
     E = res["E"].cpu().numpy()
     assert np.abs(E - np.array([x["E"] for x in g["increments"]])).max() <= TOL64
@@ -87,11 +94,11 @@ def test_workload2_all_increments(space):
     p = synthetic.workload(2)
     g = load_golden("w2")
     _check_sha(p, g)
-    print(f"[solve] workload 2 fp64 max_space {space}", flush=True)
-    plan64, r64 = ifci.solve(p, r_tol=1e-8, max_iter=600, max_space=space)
-    print(f"[solve] workload 2 mixed max_space {space}", flush=True)
+    print(f"[solve] workload 2 fp64 {space}", flush=True)
+    plan64, r64 = ifci.solve(p, r_tol=1e-8, max_iter=600, **space)
+    print(f"[solve] workload 2 mixed {space}", flush=True)
     plan32, r32 = ifci.solve(p, precision=ifci.MIXED, r_tol=1e-5, r_tol_inner=1e-5, max_iter=600,
-                             max_space=space)
+                             **space)
     torch.cuda.synchronize()
     assert [tuple(x["bodies"]) for x in g["increments"]] == [i.bodies for i in plan64.increments()]
     ref = np.array([x["E"] for x in g["increments"]])
@@ -113,7 +120,7 @@ def test_mixed_uses_fp32_stage_and_refines(space):
     import torch
     p = synthetic.workload(0, 3)
     g = load_golden("w0_r3")
-    plan, res = ifci.solve(p, precision=ifci.MIXED, r_tol=1e-7, r_tol_inner=1e-5, max_space=space, max_iter=500)
+    plan, res = ifci.solve(p, precision=ifci.MIXED, r_tol=1e-7, r_tol_inner=1e-5, **space, max_iter=500)
     torch.cuda.synchronize()
     assert int(res["status"][0]) == ifci.INC_DONE
     assert abs(float(res["E"][0]) - g["increments"][0]["E"]) <= 1e-9
@@ -142,11 +149,11 @@ def test_eviction_requeue_bitwise(space):
     again gives bitwise the energies of an undisturbed run."""
     import torch
     p = synthetic.workload(1)
-    plan, clean = ifci.solve(p, r_tol=1e-8, max_space=space, max_iter=500)
+    plan, clean = ifci.solve(p, r_tol=1e-8, **space, max_iter=500)
     n = plan.n_inc
     mask = np.zeros(n, dtype=np.uint8)
     mask[::7] = 1
-    plan2 = ifci.Plan(p, r_tol=1e-8, max_space=space, max_iter=500).attach(p.h, p.eri)
+    plan2 = ifci.Plan(p, r_tol=1e-8, **space, max_iter=500).attach(p.h, p.eri)
     e, st, it, rs = plan2.davidson(evict=mask)
     st = st.cpu().numpy()
     assert (st[mask == 1] == ifci.INC_EVICTED).all()
@@ -175,8 +182,8 @@ def test_not_converged_status():
 def test_deterministic_bitwise(space):
     import torch
     p = synthetic.workload(1)
-    _, a = ifci.solve(p, r_tol=1e-8, max_space=space, max_iter=500)
-    _, b = ifci.solve(p, r_tol=1e-8, max_space=space, max_iter=500)
+    _, a = ifci.solve(p, r_tol=1e-8, **space, max_iter=500)
+    _, b = ifci.solve(p, r_tol=1e-8, **space, max_iter=500)
     assert np.array_equal(a["E"].cpu().numpy(), b["E"].cpu().numpy())
     assert a["total"] == b["total"]
 
@@ -212,11 +219,11 @@ def test_solve_odd_shapes(name, kw, space):
     or two electrons per spin and body), FP64 and mixed, against the oracle's
     exact increment energies."""
     import torch
-    print(f"[solve] odd shapes {name} max_space {space}", flush=True)
+    print(f"[solve] odd shapes {name} {space}", flush=True)
     p = synthetic.chain(**kw)
-    plan64, r64 = ifci.solve(p, r_tol=1e-9, max_iter=500, max_space=space)
+    plan64, r64 = ifci.solve(p, r_tol=1e-9, max_iter=500, **space)
     plan32, r32 = ifci.solve(p, precision=ifci.MIXED, r_tol=3e-5, r_tol_inner=1e-5, max_iter=500,
-                             max_space=space)
+                             **space)
     torch.cuda.synchronize()
     E64 = r64["E"].cpu().numpy()
     E32 = r32["E"].cpu().numpy()
