@@ -364,6 +364,8 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 14o14e and 16o16e measurements")
     ap.add_argument("--cpu-workers", type=int, default=0, help="oracle pool size (default: min(16, cores))")
     ap.add_argument("--cpu-8o8e", type=int, default=CPU_8O8E_SAMPLE)
+    ap.add_argument("--max-space", type=int, default=SPACE,
+                    help="batched solver subspace (3: three-vector iteration, 4..16: thick-restart Davidson)")
     ap.add_argument("--n-guess", type=int, default=None,
                     help="P-space block of the three-vector solver (default: the library's)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -451,9 +453,9 @@ def main():
 
     out_detail = {}
     n_guess = a.n_guess if a.n_guess is not None else ifci.default_options().n_guess
-    mixed = measure(ifci.MIXED, ifci.BATCHED, a.steps, a.warmup, max_space=SPACE,
+    mixed = measure(ifci.MIXED, ifci.BATCHED, a.steps, a.warmup, max_space=a.max_space,
                     n_guess=n_guess) if "mixed" in legs else None
-    fp64 = measure(ifci.FP64, ifci.BATCHED, max(1, a.steps // 2), 1, max_space=SPACE,
+    fp64 = measure(ifci.FP64, ifci.BATCHED, max(1, a.steps // 2), 1, max_space=a.max_space,
                    n_guess=n_guess) if "fp64" in legs else None
     plain = measure(ifci.FP64, ifci.PLAIN, 1, 0) if "plain" in legs else None
     if "large" in legs:
@@ -484,7 +486,7 @@ def main():
         "config": {
             "workload": "16 bodies x (2 orbitals, 2 electrons), 4-body iFCI: 16x2o2e + 120x4o4e + "
                         "560x6o6e + 1820x8o8e = 2516 increments, 9,146,384 determinants, seed 2000",
-            "precision": "mixed", "solver": "batched", "max_space": SPACE, "n_guess": n_guess, "r_tol": R_TOL,
+            "precision": "mixed", "solver": "batched", "max_space": a.max_space, "n_guess": n_guess, "r_tol": R_TOL,
             "r_tol_inner": R_TOL_INNER, "accuracy_gate_Eh": TOL_UEH, "gate_reference": gate,
         },
     }

@@ -774,270 +774,6 @@ __device__ inline void subspace_solve(const Lds& L, int m) {
   __syncthreads();
 }
 
-template <int K>
-__device__ __forceinline__ void solve_one(const SolveArgs& A, int pos, char* lds, int lds_bytes) {
-  const int id = A.order[pos];
-  const IncDev d = A.inc[id];
-  Lds L = carve(lds, d, lds_bytes);
-  const double* B = A.ints + d.int_off;
-  const IntBlock ib = int_block(d.k);
-  const double* Vm = B + ib.V;
-  const int64_t ns = d.n_sym, st = d.stride;
-  double* base = A.dav + d.vec_off;
-  const int mmax = A.max_space;
-  double* Vb = base;                 // [mmax][stride]
-  double* Sb = base + mmax * st;     // [mmax][stride]
-  double* HD = base + 2 * mmax * st; // [stride]
-  double* X = HD + st;               // [stride]
-  const int tid = threadIdx.x;
-  int64_t ph[kPhases];
-#pragma unroll
-  for (int q = 0; q < kPhases; ++q) ph[q] = 0;
-  const bool trace = A.phase != nullptr;
-  int64_t t_start = trace ? clock64() : 0, t_mark = t_start;
-#define IFCI_MARK(PH)                      \
-  if (trace) {                             \
-    const int64_t now_ = clock64();        \
-    ph[PH] += now_ - t_mark;               \
-    t_mark = now_;                         \
-  }
-
-  load_increment(d, L, A.tables, B, HD);
-  argmin_block(HD, ns, L);
-  const double E0 = L.scal[0];
-  const int64_t guess = L.iscal[0];
-  for (int64_t i = tid; i < ns; i += blockDim.x) {
-    const double v = (i == guess) ? 1.0 : 0.0;
-    L.tv[i] = v;
-    Vb[i] = v;
-  }
-  for (int i = tid; i < 256; i += blockDim.x) L.G[i] = 0.0;
-  __syncthreads();
-  IFCI_MARK(kPhPrologue);
-
-  const int ew64 = et_waves_for<double, K>(d, L);
-  const int ew32 = et_waves_for<float, K>(d, L);
-  int phase = (A.precision == IFCI_MIXED) ? 32 : 64;
-  int m = 0, iters = 0, status = IFCI_INC_NOT_CONVERGED;
-  double theta = 0.0, resid = 1e300;
-  const int64_t o = (int64_t)id - A.first;  // position in the caller's range
-  const bool evict = A.evict && A.evict[o] != 0;
-  const int keep = mmax / 2 < kKeep ? mmax / 2 : kKeep;
-  bool w_built = false;  // the diagonal-pair weights of the current precision are in LDS
-
-  while (true) {
-    // sigma of the newest basis vector (in L.tv) -> S[m]
-    if (phase == 32)
-      sigma_phase<float, K>(d, L, Vm, E0, ew32, false, !w_built);
-    else
-      sigma_phase<double, K>(d, L, Vm, E0, ew64, false, !w_built);
-    w_built = true;
-    ++iters;
-    for (int64_t i = tid; i < ns; i += blockDim.x) Sb[m * st + i] = L.sp[i];
-    IFCI_MARK(kPhSigma);
-    // new column of the subspace matrix, then its eigenpairs
-    {
-      double g[kMaxSpace];
-#pragma unroll
-      for (int j = 0; j < kMaxSpace; ++j) g[j] = 0.0;
-      for (int64_t i = tid; i < ns; i += blockDim.x) {
-        const double s = L.sp[i];
-#pragma unroll
-        for (int j = 0; j < kMaxSpace; ++j)
-          if (j <= m) g[j] += Vb[j * st + i] * s;
-      }
-      block_sum<kMaxSpace>(g, L.red, L.scal);
-      if (tid <= m) {
-        L.G[tid * 16 + m] = L.scal[tid];
-        L.G[m * 16 + tid] = L.scal[tid];
-      }
-      __syncthreads();
-      subspace_solve(L, m);
-      theta = L.scal[20];
-    }
-    IFCI_MARK(kPhSubspace);
-    const bool restart = (m + 1 == mmax);
-    // pass A: Ritz vector x, its sigma, residual, preconditioned correction
-    double acc[kMaxSpace + 2];
-#pragma unroll
-    for (int j = 0; j < kMaxSpace + 2; ++j) acc[j] = 0.0;
-    {
-      double yy[kMaxSpace];
-#pragma unroll
-      for (int j = 0; j < kMaxSpace; ++j) yy[j] = (j <= m) ? L.y[j] : 0.0;
-      for (int64_t i = tid; i < ns; i += blockDim.x) {
-        double vv[kMaxSpace];
-        double x = 0.0, sx = 0.0;
-#pragma unroll
-        for (int j = 0; j < kMaxSpace; ++j) {
-          if (j <= m) {
-            vv[j] = Vb[j * st + i];
-            x += yy[j] * vv[j];
-            sx += yy[j] * Sb[j * st + i];
-          } else {
-            vv[j] = 0.0;
-          }
-        }
-        const double r = sx - theta * x;
-        double den = theta - (HD[i] - E0);
-        if (fabs(den) < 1e-8) den = (den < 0.0) ? -1e-8 : 1e-8;
-        const double t = r / den;
-        acc[kMaxSpace] += r * r;
-        acc[kMaxSpace + 1] += t * t;
-#pragma unroll
-        for (int j = 0; j < kMaxSpace; ++j) acc[j] += vv[j] * t;
-        L.tv[i] = t;
-        X[i] = x;
-      }
-    }
-    block_sum<kMaxSpace + 2>(acc, L.red, L.scal);
-    resid = sqrt(L.scal[kMaxSpace]);
-    const double tt0 = L.scal[kMaxSpace + 1];
-    if (tid < kMaxSpace) L.cf[tid] = (tid <= m) ? L.scal[tid] : 0.0;
-    __syncthreads();
-    IFCI_MARK(kPhPassA);
-
-    const double tol = (phase == 32) ? A.r_tol_inner : A.r_tol;
-    if (evict) {
-      status = IFCI_INC_EVICTED;
-      break;
-    }
-    if (resid <= tol) {
-      if (phase == 32) {
-        // FP64 refinement: restart from x with FP64 sigma
-        phase = 64;
-        w_built = false;
-        for (int64_t i = tid; i < ns; i += blockDim.x) {
-          const double x = X[i];
-          L.tv[i] = x;
-          Vb[i] = x;
-        }
-        for (int i = tid; i < 256; i += blockDim.x) L.G[i] = 0.0;
-        m = 0;
-        __syncthreads();
-        if (iters >= A.max_iter) break;
-        continue;
-      }
-      status = IFCI_INC_DONE;
-      break;
-    }
-    if (iters >= A.max_iter) break;
-    int mb = m;
-    if (restart) {
-      // thick restart: keep the `keep` lowest Ritz vectors and their sigmas
-      for (int64_t i = tid; i < ns; i += blockDim.x) {
-        double vv[kMaxSpace];
-#pragma unroll
-        for (int j = 0; j < kMaxSpace; ++j) vv[j] = (j <= m) ? Vb[j * st + i] : 0.0;
-        for (int kk = 0; kk < keep; ++kk) {
-          const int c = L.perm[kk];
-          double v = 0.0;
-#pragma unroll
-          for (int j = 0; j < kMaxSpace; ++j)
-            if (j <= m) v += L.Qp[j * 16 + c] * vv[j];
-          Vb[kk * st + i] = v;
-        }
-#pragma unroll
-        for (int j = 0; j < kMaxSpace; ++j) vv[j] = (j <= m) ? Sb[j * st + i] : 0.0;
-        for (int kk = 0; kk < keep; ++kk) {
-          const int c = L.perm[kk];
-          double v = 0.0;
-#pragma unroll
-          for (int j = 0; j < kMaxSpace; ++j)
-            if (j <= m) v += L.Qp[j * 16 + c] * vv[j];
-          Sb[kk * st + i] = v;
-        }
-      }
-      double cnew = 0.0;
-      if (tid < keep) {
-        const int c = L.perm[tid];
-        for (int j = 0; j <= m; ++j) cnew += L.Qp[j * 16 + c] * L.cf[j];
-      }
-      __syncthreads();
-      // the kept Ritz vectors diagonalise the new subspace matrix
-      for (int i = tid; i < 256; i += blockDim.x) {
-        L.G[i] = 0.0;
-        L.Qp[i] = ((i >> 4) == (i & 15)) ? 1.0 : 0.0;
-      }
-      if (tid < kMaxSpace) L.cf[tid] = (tid < keep) ? cnew : 0.0;
-      __syncthreads();
-      if (tid < keep) {
-        L.G[tid * 16 + tid] = L.ev[tid];
-        L.Lam[tid] = L.ev[tid];
-      }
-      mb = keep - 1;
-      __syncthreads();
-      IFCI_MARK(kPhRestart);
-    }
-    // pass B: project out the basis (classical Gram-Schmidt), with a second
-    // pass when the norm drops by more than 1/sqrt(2) (DGKS criterion)
-    double acc2[kMaxSpace + 1];
-#pragma unroll
-    for (int j = 0; j < kMaxSpace + 1; ++j) acc2[j] = 0.0;
-    {
-      double cc[kMaxSpace];
-#pragma unroll
-      for (int j = 0; j < kMaxSpace; ++j) cc[j] = (j <= mb) ? L.cf[j] : 0.0;
-      for (int64_t i = tid; i < ns; i += blockDim.x) {
-        double vv[kMaxSpace];
-        double t = L.tv[i];
-#pragma unroll
-        for (int j = 0; j < kMaxSpace; ++j) {
-          vv[j] = (j <= mb) ? Vb[j * st + i] : 0.0;
-          t -= cc[j] * vv[j];
-        }
-        L.tv[i] = t;
-        acc2[kMaxSpace] += t * t;
-#pragma unroll
-        for (int j = 0; j < kMaxSpace; ++j) acc2[j] += vv[j] * t;
-      }
-    }
-    block_sum<kMaxSpace + 1>(acc2, L.red, L.scal);
-    double tt = L.scal[kMaxSpace];
-    if (tt < 0.5 * tt0) {
-      double c2[kMaxSpace];
-#pragma unroll
-      for (int j = 0; j < kMaxSpace; ++j) c2[j] = (j <= mb) ? L.scal[j] : 0.0;
-      __syncthreads();
-      double acc3[1] = {0.0};
-      for (int64_t i = tid; i < ns; i += blockDim.x) {
-        double t = L.tv[i];
-#pragma unroll
-        for (int j = 0; j < kMaxSpace; ++j)
-          if (j <= mb) t -= c2[j] * Vb[j * st + i];
-        L.tv[i] = t;
-        acc3[0] += t * t;
-      }
-      block_sum<1>(acc3, L.red, L.scal);
-      tt = L.scal[0];
-    }
-    __syncthreads();
-    if (!(tt > 1e-28)) break;  // no new direction: stagnated
-    const double inv = 1.0 / sqrt(tt);
-    m = mb + 1;
-    for (int64_t i = tid; i < ns; i += blockDim.x) {
-      const double t = L.tv[i] * inv;
-      L.tv[i] = t;
-      Vb[m * st + i] = t;
-    }
-    __syncthreads();
-    IFCI_MARK(kPhOrtho);
-  }
-  if (trace && tid == 0) {
-    ph[kPhIters] = iters;
-    ph[kPhTotal] = clock64() - t_start;
-#pragma unroll
-    for (int q = 0; q < kPhases; ++q) A.phase[(int64_t)id * kPhases + q] = ph[q];
-  }
-#undef IFCI_MARK
-  if (tid == 0) {
-    const double e = theta + E0 + B[ib.misc + 0] + A.e_const;
-    if (A.e_out) A.e_out[o] = e;
-    if (A.status_out) A.status_out[o] = status;
-    if (A.iters_out) A.iters_out[o] = iters;
-    if (A.resid_out) A.resid_out[o] = resid;
-  }
-}
 
 // Lowest eigenpair of a symmetric 3 x 3 matrix g (g[2][2] = 1e30 with a
 // zero third row and column marks a 2 x 2 problem).  2 x 2: closed form.
@@ -1704,20 +1440,411 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
 }
 
 // One kernel per solver so that each gets its own register allocation.
+// Thick-restart Davidson with the vector work of the three-vector solver:
+// every thread owns NE entries of each vector, and the basis V and its
+// sigmas S (mmax vectors each, global memory) are streamed in passes, each
+// over the basis index with the entries unrolled: (A) x = V y, Ax = S y,
+// the residual and the preconditioned correction t (with the P-space block
+// when there is one); (B) the overlaps c_j = V_j.t and d_j = S_j.t, summed
+// per wave as they are formed; at a restart (R) the kept Ritz vectors and
+// their sigmas, written over the first slots; (C) classical Gram-Schmidt
+// of t against the basis, repeated when its norm drops by more than
+// 1/sqrt 2.  The new column of the subspace matrix needs no further pass:
+// with t' = t - sum_k c_k B_k, S_j.t' = d_j - sum_k c_k G[k][j]; only its
+// diagonal entry waits for the new sigma (one dot product).  The residual
+// is formed from the stored vectors, so the convergence test does not
+// depend on the subspace matrix being exact.  Nothing but scalars stays in
+// registers across a sigma.
+template <int K>
+__device__ __forceinline__ void solve_dav(const SolveArgs& A, int pos, char* lds, int lds_bytes) {
+  const int id = A.order[pos];
+  const IncDev d = A.inc[id];
+  Lds L = carve(lds, d, lds_bytes);
+  const double* B = A.ints + d.int_off;
+  const IntBlock ib = int_block(d.k);
+  const double* Vm = B + ib.V;
+  const int64_t ns = d.n_sym, st = d.stride;
+  double* base = A.dav + d.vec_off;
+  const int mmax = A.max_space;
+  double* HD = base + 2 * mmax * st;
+  double* X = HD + st;
+  const int tid = threadIdx.x;
+  int64_t ph[kPhases];
+#pragma unroll
+  for (int q = 0; q < kPhases; ++q) ph[q] = 0;
+  const bool trace = A.phase != nullptr;
+  int64_t t_start = trace ? clock64() : 0, t_mark = t_start;
+#define IFCI_MARK(PH)                      \
+  if (trace) {                             \
+    const int64_t now_ = clock64();        \
+    ph[PH] += now_ - t_mark;               \
+    t_mark = now_;                         \
+  }
+
+  load_increment(d, L, A.tables, B, HD);
+  argmin_block(HD, ns, L);
+  const double E0 = L.scal[0];
+  const int64_t guess = L.iscal[0];
+  constexpr int NE = (max_strings(K) * (max_strings(K) + 1) / 2 + kBatchThreads - 1) / kBatchThreads;
+  int bsp = 0;
+  float* Ug = (float*)(base + ps_image_offset(st, mmax));
+  const int P = A.n_guess > 1 ? ps_size<K>(d, L, A.n_guess) : 0;
+  float* Us = (float*)(L.et + ps_scratch_offset(d));
+  if (P > 0) {
+    uint64_t pk;
+    ps_build<K, NE>(d, L, B, HD, E0, P, pk, bsp);
+    IFCI_MARK(kPhPrologue);
+    ps_eigen<K, NE>(d, L, P, pk, Ug, base, bsp);
+    IFCI_MARK(kPhRestart);
+  } else {
+    for (int64_t i = tid; i < ns; i += blockDim.x) {
+      const double v = (i == guess) ? 1.0 : 0.0;
+      L.tv[i] = v;
+      base[i] = v;
+    }
+  }
+  for (int i = tid; i < 256; i += blockDim.x) L.G[i] = 0.0;
+  __syncthreads();
+  IFCI_MARK(kPhPrologue);
+
+  const int nsi = (int)ns, sti = (int)st, mst = mmax * (int)st;
+  const int lane = tid & 63, wave = tid >> 6, nw = kBatchThreads >> 6;
+  const int ew64 = et_waves_for<double, K>(d, L);
+  const int ew32 = et_waves_for<float, K>(d, L);
+  int phase = (A.precision == IFCI_MIXED) ? 32 : 64;
+  int m = 0, iters = 0, status = IFCI_INC_NOT_CONVERGED;
+  double theta = 0.0, resid = 1e300;
+  const int64_t o = (int64_t)id - A.first;
+  const bool evict = A.evict && A.evict[o] != 0;
+  const int keep = mmax / 2 < kKeep ? mmax / 2 : kKeep;
+  bool staged = false;
+  bool w_built = false;
+  // per-wave partial overlaps [kMaxSpace][2][8]: the eigenvector scratch of
+  // subspace_solve, free once it returns
+  double* wpart = L.Qv;
+
+  while (true) {
+    // ---- sigma of v_m -> S_m, and G[m][m]
+    if (phase == 32)
+      sigma_phase<float, K>(d, L, Vm, E0, ew32, staged, !w_built);
+    else
+      sigma_phase<double, K>(d, L, Vm, E0, ew64, staged, !w_built);
+    w_built = true;
+    staged = false;
+    ++iters;
+    int tix = tid;
+    asm volatile("" : "+v"(tix));
+    {
+      double acc[1] = {0.0};
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const int i = tix + e * kBatchThreads;
+        if (i < nsi) {
+          const double sv = L.sp[i];
+          acc[0] += base[m * sti + i] * sv;
+          base[mst + m * sti + i] = sv;
+        }
+      }
+      block_sum_1b<1>(acc, L.red, bsp);
+      if (tid == 0) L.G[m * 16 + m] = acc[0];
+    }
+    // the FP32 eigenvectors of the P-space block back into LDS
+    if (P > 0)
+      for (int u = tix; u < P * P / 4; u += kBatchThreads) ((float4*)Us)[u] = ((const float4*)Ug)[u];
+    __syncthreads();
+    IFCI_MARK(kPhSigma);
+    subspace_solve(L, m);
+    theta = L.scal[20];
+    IFCI_MARK(kPhSubspace);
+    const bool restart = (m + 1 == mmax);
+    // ---- pass A: x = V y, Ax = S y, r, t
+    double rx[NE], rax[NE], rt[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) rx[e] = rax[e] = 0.0;
+#pragma unroll 4
+    for (int j = 0; j <= m; ++j) {
+      const double yj = L.y[j];
+      const double* vj = base + j * sti;
+      const double* sj = base + mst + j * sti;
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const int i = min(tix + e * kBatchThreads, nsi - 1);
+        rx[e] += yj * vj[i];
+        rax[e] += yj * sj[i];
+      }
+    }
+    double accr = 0.0;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const bool in = tix + e * kBatchThreads < nsi;
+      const double r = in ? rax[e] - theta * rx[e] : 0.0;
+      rt[e] = r;
+      accr += r * r;
+      if (P > 0 && in) L.tv[tix + e * kBatchThreads] = r;
+    }
+    const double ps_h = P > 0 ? L.plam[kPsMax] : -1e300;
+    const int ps_i = P > 0 ? L.pidx[P - 1] : -1;
+    if (P > 0) ps_apply(Us, P, theta, L.plam, L.pidx, L.tv, L.Gs);
+    double acct = 0.0;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int i = tix + e * kBatchThreads;
+      const double hd = HD[min(i, nsi - 1)];
+      double den = theta - (hd - E0);
+      if (fabs(den) < 1e-8) den = (den < 0.0) ? -1e-8 : 1e-8;
+      const bool in_p = i < nsi && (hd < ps_h || (hd == ps_h && i <= ps_i));
+      const double t = in_p ? L.tv[i] : rt[e] / den;
+      rt[e] = i < nsi ? t : 0.0;
+      acct += rt[e] * rt[e];
+    }
+    IFCI_MARK(kPhPassA);
+    // ---- pass B: c_j = V_j.t, d_j = S_j.t (j <= m), wave sums into wpart
+#pragma unroll 4
+    for (int j = 0; j <= m; ++j) {
+      const double* vj = base + j * sti;
+      const double* sj = base + mst + j * sti;
+      double c = 0.0, dd = 0.0;
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const int i = min(tix + e * kBatchThreads, nsi - 1);
+        c += vj[i] * rt[e];
+        dd += sj[i] * rt[e];
+      }
+      c = wave_sum(c);
+      dd = wave_sum(dd);
+      if (lane == 0) {
+        wpart[(2 * j) * 8 + wave] = c;
+        wpart[(2 * j + 1) * 8 + wave] = dd;
+      }
+    }
+    double tt0;
+    {
+      double a2[2] = {accr, acct};
+      block_sum_1b<2>(a2, L.red, bsp);
+      resid = sqrt(a2[0]);
+      tt0 = a2[1];
+      // Gs [0, 16) c, [16, 32) d: the wave partials in a fixed order
+      if (tid < 2 * (m + 1)) {
+        const int j = tid >> 1, w = tid & 1;
+        double sum = 0.0;
+        for (int q = 0; q < nw; ++q) sum += wpart[(2 * j + w) * 8 + q];
+        L.Gs[w * kMaxSpace + j] = sum;
+      }
+    }
+    IFCI_MARK(kPhRestart);
+
+    const double tol = (phase == 32) ? A.r_tol_inner : A.r_tol;
+    bool done = false;
+    if (evict) {
+      status = IFCI_INC_EVICTED;
+      done = true;
+    } else if (resid <= tol && phase == 64) {
+      status = IFCI_INC_DONE;
+      done = true;
+    } else if (iters >= A.max_iter) {
+      done = true;
+    }
+    if (done) {
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const int i = tix + e * kBatchThreads;
+        if (i < nsi) X[i] = rx[e];
+      }
+      break;
+    }
+    if (resid <= tol) {
+      // FP64 refinement: restart from x with FP64 sigma
+      phase = 64;
+      w_built = false;
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const int i = tix + e * kBatchThreads;
+        if (i < nsi) {
+          L.tv[i] = rx[e];
+          base[i] = rx[e];
+        }
+      }
+      for (int i = tid; i < 256; i += blockDim.x) L.G[i] = 0.0;
+      m = 0;
+      __syncthreads();
+      continue;
+    }
+    __syncthreads();
+    // ---- restart: the keep lowest Ritz vectors and their sigmas over slots
+    // 0 .. keep-1 (slot 0: x and Ax from pass A), each entry read in full
+    // before it is written
+    if (restart) {
+      int qc[kKeep];
+#pragma unroll
+      for (int k = 0; k < kKeep; ++k) qc[k] = L.perm[k < keep ? k : 0];
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const int i = min(tix + e * kBatchThreads, nsi - 1);
+        const bool in = tix + e * kBatchThreads < nsi;
+        double nv[kKeep], nsg[kKeep];
+#pragma unroll
+        for (int k = 0; k < kKeep; ++k) nv[k] = nsg[k] = 0.0;
+        for (int j = 0; j <= m; ++j) {
+          const double v = base[j * sti + i], sv = base[mst + j * sti + i];
+#pragma unroll
+          for (int k = 1; k < kKeep; ++k) {
+            const double q = L.Qp[j * 16 + qc[k]];
+            nv[k] += q * v;
+            nsg[k] += q * sv;
+          }
+        }
+        if (in) {
+          base[i] = rx[e];
+          base[mst + i] = rax[e];
+#pragma unroll
+          for (int k = 1; k < kKeep; ++k)
+            if (k < keep) {
+              base[k * sti + i] = nv[k];
+              base[mst + k * sti + i] = nsg[k];
+            }
+        }
+      }
+    }
+    // overlaps with the basis t is orthogonalised against, into Gs [64, 80)
+    // (c) and [96, 112) (d): after a restart the kept Ritz vectors, c' = Q^T c
+    // and d' = Q^T d, and the subspace matrix becomes diag of their values
+    const int mb = restart ? keep - 1 : m;
+    if (tid < kMaxSpace) {
+      double c = 0.0, dd = 0.0;
+      if (restart) {
+        if (tid < keep) {
+          const int q = L.perm[tid];
+          for (int j = 0; j <= m; ++j) {
+            c += L.Qp[j * 16 + q] * L.Gs[j];
+            dd += L.Qp[j * 16 + q] * L.Gs[kMaxSpace + j];
+          }
+        }
+      } else if (tid <= m) {
+        c = L.Gs[tid];
+        dd = L.Gs[kMaxSpace + tid];
+      }
+      L.Gs[64 + tid] = c;
+      L.Gs[96 + tid] = dd;
+    }
+    __syncthreads();
+    if (restart) {
+      for (int i = tid; i < 256; i += blockDim.x) {
+        L.G[i] = 0.0;
+        L.Qp[i] = ((i >> 4) == (i & 15)) ? 1.0 : 0.0;
+      }
+      __syncthreads();
+      if (tid < keep) {
+        L.G[tid * 16 + tid] = L.ev[tid];
+        L.Lam[tid] = L.ev[tid];
+      }
+    }
+    // ---- pass C: t -= sum_j c_j B_j; if its norm dropped below half,
+    // the overlaps with t' and a second subtraction
+    double tt = 0.0;
+#pragma unroll 1
+    for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll 2
+      for (int j = 0; j <= mb; ++j) {
+        const double c = L.Gs[(pass == 0 ? 64 : 0) + j];
+        const double* bj = base + j * sti;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) rt[e] -= c * bj[min(tix + e * kBatchThreads, nsi - 1)];
+      }
+      double a1[1] = {0.0};
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        rt[e] = tix + e * kBatchThreads < nsi ? rt[e] : 0.0;
+        a1[0] += rt[e] * rt[e];
+      }
+      block_sum_1b<1>(a1, L.red, bsp);
+      tt = a1[0];
+      if (pass == 1 || !(tt < 0.5 * tt0)) break;
+      // overlaps B_j.t' into Gs [0, 16), accumulated into c
+#pragma unroll 2
+      for (int j = 0; j <= mb; ++j) {
+        const double* bj = base + j * sti;
+        double c = 0.0;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) c += bj[min(tix + e * kBatchThreads, nsi - 1)] * rt[e];
+        c = wave_sum(c);
+        if (lane == 0) wpart[j * 8 + wave] = c;
+      }
+      __syncthreads();
+      if (tid <= mb) {
+        double sum = 0.0;
+        for (int q = 0; q < nw; ++q) sum += wpart[tid * 8 + q];
+        L.Gs[tid] = sum;
+        L.Gs[64 + tid] += sum;
+      }
+      __syncthreads();
+    }
+    if (!(tt > 1e-28)) {  // no new direction: stagnated
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const int i = tix + e * kBatchThreads;
+        if (i < nsi) X[i] = rx[e];
+      }
+      break;
+    }
+    const double inv = 1.0 / sqrt(tt);
+    // new column of the subspace matrix: S_j.t' / |t'| with
+    // S_j.t' = d_j - sum_k c_k G[k][j] (c accumulated over both passes)
+    const int mn = mb + 1;
+    if (tid <= mb) {
+      double g = L.Gs[96 + tid];
+      for (int k = 0; k <= mb; ++k) g -= L.Gs[64 + k] * L.G[k * 16 + tid];
+      g *= inv;
+      L.G[tid * 16 + mn] = g;
+      L.G[mn * 16 + tid] = g;
+    }
+    // the new basis vector: global slot mn and the next sigma's input
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int i = tix + e * kBatchThreads;
+      const double t = rt[e] * inv;
+      if (i < nsi) {
+        base[mn * sti + i] = t;
+        if (phase == 32)
+          stage_entry<float>(d, L, i, t);
+        else
+          stage_entry<double>(d, L, i, t);
+      }
+    }
+    m = mn;
+    staged = true;
+    __syncthreads();
+    IFCI_MARK(kPhOrtho);
+  }
+  if (trace && tid == 0) {
+    ph[kPhIters] = iters;
+    ph[kPhTotal] = clock64() - t_start;
+#pragma unroll
+    for (int q = 0; q < kPhases; ++q) A.phase[(int64_t)id * kPhases + q] = ph[q];
+  }
+#undef IFCI_MARK
+  if (tid == 0) {
+    const double e = theta + E0 + B[ib.misc + 0] + A.e_const;
+    if (A.e_out) A.e_out[o] = e;
+    if (A.status_out) A.status_out[o] = status;
+    if (A.iters_out) A.iters_out[o] = iters;
+    if (A.resid_out) A.resid_out[o] = resid;
+  }
+}
+
 __global__ void __launch_bounds__(kBatchThreads) batched_kernel(SolveArgs A, int lds_bytes) {
   extern __shared__ __align__(16) char lds[];
   const int pos = blockIdx.x;
   if (pos >= A.count) return;
   const int k = A.inc[A.order[pos]].k;
   switch (k) {
-    case 1: solve_one<1>(A, pos, lds, lds_bytes); break;
-    case 2: solve_one<2>(A, pos, lds, lds_bytes); break;
-    case 3: solve_one<3>(A, pos, lds, lds_bytes); break;
-    case 4: solve_one<4>(A, pos, lds, lds_bytes); break;
-    case 5: solve_one<5>(A, pos, lds, lds_bytes); break;
-    case 6: solve_one<6>(A, pos, lds, lds_bytes); break;
-    case 7: solve_one<7>(A, pos, lds, lds_bytes); break;
-    case 8: solve_one<8>(A, pos, lds, lds_bytes); break;
+    case 1: solve_dav<1>(A, pos, lds, lds_bytes); break;
+    case 2: solve_dav<2>(A, pos, lds, lds_bytes); break;
+    case 3: solve_dav<3>(A, pos, lds, lds_bytes); break;
+    case 4: solve_dav<4>(A, pos, lds, lds_bytes); break;
+    case 5: solve_dav<5>(A, pos, lds, lds_bytes); break;
+    case 6: solve_dav<6>(A, pos, lds, lds_bytes); break;
+    case 7: solve_dav<7>(A, pos, lds, lds_bytes); break;
+    case 8: solve_dav<8>(A, pos, lds, lds_bytes); break;
     default: break;
   }
 }

@@ -144,86 +144,123 @@ constexpr double kSqrt2 = 1.4142135623730950488;
 constexpr double kRSqrt2 = 0.70710678118654752440;
 
 // Eigen-decomposition of the symmetric n x n matrix A (row stride 16,
-// n <= 16) by cyclic Jacobi rotations (Golub & Van Loan, symmetric Schur
-// decomposition), accumulating the rotations into Q (stride 16), which the
-// caller initialises (identity, or eigenvectors of a previous nearby matrix
-// to warm start).  Rotations whose off-diagonal element is below
-// 1e-15 ||A||_F are skipped; sweeps stop when none is applied.
-// Executed by one full wavefront; lane i owns row i.  Returns the sorted
-// eigenvalues in evals, their columns of Q in perm, and the lowest pair in
-// theta / y.
+// n <= 16) by parallel cyclic Jacobi (Golub & Van Loan, symmetric Schur
+// rotations in the Brent-Luk circle ordering), accumulating the rotations
+// into Q (stride 16), which the caller initialises (identity, or
+// eigenvectors of a previous nearby matrix to warm start).  An odd n is
+// padded with a decoupled index whose diagonal entry lies far above the
+// spectrum (its row and column of A and Q are overwritten).  Each round
+// rotates N / 2 disjoint planes at once: lanes below N / 2 compute the
+// planes' rotations and pass them on by shuffles, lane L updates the 2 x 2
+// block (L / 8, L % 8) of A and rows L / 8 and L / 8 + 8 of Q in plane L % 8.
+// Pivots below 1e-15 ||A||_F are not rotated (FP64 rounding keeps
+// regenerating off-diagonal noise near 1e-16 ||A||); sweeps stop after one
+// whose squared pivots sum below 1e-24 ||A||_F^2 (the quadratic convergence
+// of the cyclic method leaves the off-diagonal part at rounding level after
+// such a sweep).  Executed by one
+// full wavefront, which orders its own LDS accesses, so no workgroup
+// barrier is needed.  Returns the sorted eigenvalues in evals, their
+// columns of Q in perm, and the lowest pair in theta / y.
 __device__ inline void jacobi_warm(double* A, double* Q, int n, double* theta, double* y, double* evals,
                                    int* perm) {
   const int lane = threadIdx.x & 63;
+  const int N = n + (n & 1), H = N >> 1, m = N - 1;
   __builtin_amdgcn_wave_barrier();
-  // rotations below 1e-15 ||A||_F are skipped: the eigenvalue error that
-  // leaves is of order 1e-30 ||A||^2 / gap, and FP64 rounding keeps
-  // regenerating off-diagonal noise near 1e-16 ||A|| that must not be chased
   double f2 = 0.0;
   if (lane < n)
     for (int j = 0; j < n; ++j) f2 += A[lane * 16 + j] * A[lane * 16 + j];
   f2 = wave_sum(f2);
+  if (n & 1) {
+    // decoupled padding index n
+    const double big = 1e3 * (1.0 + sqrt(f2));
+    if (lane < 16) {
+      A[lane * 16 + n] = (lane == n) ? big : 0.0;
+      A[n * 16 + lane] = (lane == n) ? big : 0.0;
+      Q[lane * 16 + n] = (lane == n) ? 1.0 : 0.0;
+      Q[n * 16 + lane] = (lane == n) ? 1.0 : 0.0;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
   const double tol = 1e-15 * sqrt(f2);
-  for (int sweep = 0; sweep < 12; ++sweep) {
-    bool rotated = false;
-    for (int p = 0; p < n - 1; ++p) {
-      // which q > p start this row above the threshold
-      __builtin_amdgcn_wave_barrier();
-      const bool big = lane > p && lane < n && fabs(A[p * 16 + lane]) > tol;
-      uint64_t mask = __ballot(big);
-      while (mask) {
-        const int q = __builtin_ctzll(mask);
-        mask &= mask - 1;
-        __builtin_amdgcn_wave_barrier();
+  const int kr = lane >> 3, kc = lane & 7;
+  const bool blk = kr < H && kc < H;
+  for (int sweep = 0; sweep < 12 && N > 1; ++sweep) {
+    double piv2 = 0.0;
+    for (int s = 0; s < m; ++s) {
+      // plane k of round s: (P - 1, s) for k = 0, else (s + k, s - k) mod (N - 1)
+      auto plane = [&](int k, int* p, int* q) {
+        int x, yv;
+        if (k == 0) {
+          x = m;
+          yv = s;
+        } else {
+          x = s + k;
+          if (x >= m) x -= m;
+          yv = s - k + m;
+          if (yv >= m) yv -= m;
+        }
+        *p = x < yv ? x : yv;
+        *q = x < yv ? yv : x;
+      };
+      double c = 1.0, sn = 0.0;
+      if (lane < H) {
+        int p, q;
+        plane(lane, &p, &q);
         const double apq = A[p * 16 + q];
-        if (!(fabs(apq) > tol)) continue;
-        const double app = A[p * 16 + p], aqq = A[q * 16 + q];
-        rotated = true;
-        const double tau = (aqq - app) / (2.0 * apq);
-        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
-        __builtin_amdgcn_wave_barrier();
-        if (lane < n && lane != p && lane != q) {
-          const double aip = A[lane * 16 + p], aiq = A[lane * 16 + q];
-          const double nip = c * aip - s * aiq, niq = s * aip + c * aiq;
-          A[lane * 16 + p] = nip;
-          A[p * 16 + lane] = nip;
-          A[lane * 16 + q] = niq;
-          A[q * 16 + lane] = niq;
-        }
-        if (lane == p) {
-          A[p * 16 + p] = app - t * apq;
-          A[p * 16 + q] = 0.0;
-          A[q * 16 + p] = 0.0;
-        }
-        if (lane == q) A[q * 16 + q] = aqq + t * apq;
-        if (lane < n) {
-          const double vp = Q[lane * 16 + p], vq = Q[lane * 16 + q];
-          Q[lane * 16 + p] = c * vp - s * vq;
-          Q[lane * 16 + q] = s * vp + c * vq;
+        piv2 += apq * apq;
+        if (fabs(apq) > tol) {
+          const double tau = (A[q * 16 + q] - A[p * 16 + p]) / (2.0 * apq);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          sn = t * c;
         }
       }
+      const double c1 = __shfl(c, kr & 7, 64), s1 = __shfl(sn, kr & 7, 64);
+      const double c2 = __shfl(c, kc, 64), s2 = __shfl(sn, kc, 64);
+      __builtin_amdgcn_wave_barrier();
+      if (blk) {
+        int p1, q1, p2, q2;
+        plane(kr, &p1, &q1);
+        plane(kc, &p2, &q2);
+        const double a = A[p1 * 16 + p2], b = A[p1 * 16 + q2], e = A[q1 * 16 + p2], f = A[q1 * 16 + q2];
+        const double a1 = c2 * a - s2 * b, b1 = s2 * a + c2 * b;
+        const double e1 = c2 * e - s2 * f, f1 = s2 * e + c2 * f;
+        A[p1 * 16 + p2] = c1 * a1 - s1 * e1;
+        A[q1 * 16 + p2] = s1 * a1 + c1 * e1;
+        A[p1 * 16 + q2] = c1 * b1 - s1 * f1;
+        A[q1 * 16 + q2] = s1 * b1 + c1 * f1;
+      }
+      if (kc < H) {
+        int p, q;
+        plane(kc, &p, &q);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int i = kr + 8 * h;
+          if (i < N) {
+            const double vp = Q[i * 16 + p], vq = Q[i * 16 + q];
+            Q[i * 16 + p] = c2 * vp - s2 * vq;
+            Q[i * 16 + q] = s2 * vp + c2 * vq;
+          }
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
     }
-    __builtin_amdgcn_wave_barrier();
-    if (!rotated) break;
+    piv2 = wave_sum(piv2);
+    if (!(piv2 > 1e-24 * f2)) break;
   }
   __builtin_amdgcn_wave_barrier();
   // eigenvalues in increasing order (ties by index): perm[i] is the column
-  // of Q holding the i-th lowest
-  if (lane == 0) {
-    for (int i = 0; i < n; ++i) perm[i] = i;
+  // of Q holding the i-th lowest; lane j finds the rank of eigenvalue j
+  if (lane < n) {
+    const double vj = A[lane * 16 + lane];
+    int rank = 0;
     for (int i = 0; i < n; ++i) {
-      int b = i;
-      for (int j = i + 1; j < n; ++j) {
-        const double vj = A[perm[j] * 16 + perm[j]], vb = A[perm[b] * 16 + perm[b]];
-        if (vj < vb || (vj == vb && perm[j] < perm[b])) b = j;
-      }
-      const int t = perm[i];
-      perm[i] = perm[b];
-      perm[b] = t;
-      evals[i] = A[perm[i] * 16 + perm[i]];
+      const double vi = A[i * 16 + i];
+      rank += (vi < vj || (vi == vj && i < lane)) ? 1 : 0;
     }
-    *theta = evals[0];
+    perm[rank] = lane;
+    evals[rank] = vj;
+    if (rank == 0) *theta = vj;
   }
   __builtin_amdgcn_wave_barrier();
   if (lane < n) y[lane] = Q[lane * 16 + perm[0]];

@@ -12,11 +12,12 @@ from tests.helpers import active_hamiltonian, load_golden
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-9
-# max_space 12: thick-restart Davidson; max_space 3: the {x, w, p} solver,
-# started from the lowest determinant with the diagonal preconditioner
+# max_space 12: thick-restart Davidson; max_space 3: the {x, w, p} solver;
+# each started from the lowest determinant with the diagonal preconditioner
 # (n_guess 0) or from the lowest eigenvector of the 64-determinant P-space
 # block with that block's exact inverse as preconditioner (the default)
-SPACES = [pytest.param(dict(max_space=12), id="davidson12"),
+SPACES = [pytest.param(dict(max_space=12, n_guess=0), id="davidson12"),
+          pytest.param(dict(max_space=12), id="davidson12_pspace"),
           pytest.param(dict(max_space=3, n_guess=0), id="3vec"),
           pytest.param(dict(max_space=3), id="3vec_pspace")]
 
