@@ -458,6 +458,20 @@ def main():
     fp64 = measure(ifci.FP64, ifci.BATCHED, max(1, a.steps // 2), 1, max_space=a.max_space,
                    n_guess=n_guess) if "fp64" in legs else None
     plain = measure(ifci.FP64, ifci.PLAIN, 1, 0) if "plain" in legs else None
+    # the tuner's per-shape settings (tuning.json, applied by Plan) against
+    # the built-in choices
+    tuning = ifci.load_tuning()
+    if tuning and "mixed" in legs:
+        untuned = measure(ifci.MIXED, ifci.BATCHED, max(1, a.steps // 2), 1, max_space=a.max_space,
+                          n_guess=n_guess, tuning=None)
+        out_detail["tuning"] = {
+            "cache": "paper_2307_10675_amd/tuning.json",
+            "entries": {f"k{k}_{'mixed' if p == ifci.MIXED else 'fp64'}": {"ps_block": v[0], "e_waves": v[1]}
+                        for (k, p), v in sorted(tuning.items())},
+            "tuned_kernel_ms": mixed["kernel_ms"], "default_kernel_ms": untuned["kernel_ms"],
+            "tuned_inc_per_s": mixed["inc_per_s"], "default_inc_per_s": untuned["inc_per_s"],
+            "default_n_ok": untuned["n_ok"],
+        }
     if "large" in legs:
         out_detail["large_sigma"] = large_sigma(torch, ifci, synthetic)
         out_detail["large_sigma_16o"] = large_sigma(torch, ifci, synthetic, n_orb=16, reps=3)

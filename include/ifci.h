@@ -287,6 +287,23 @@ ifci_status ifci_rdm(ifci_plan_t plan, const double* weights, double* dE_dh, dou
  * The caller zeroes the buffer; it must outlive the next ifci_davidson. */
 ifci_status ifci_set_phase_counters(ifci_plan_t plan, int64_t* counters, int64_t n);
 
+/* Tuning of the on-chip solvers (increments of up to 8 active orbitals) for
+ * increments of k active orbitals.  precision selects the row: IFCI_FP64
+ * for FP64 plans and for every FP64 sigma, IFCI_MIXED for mixed plans and
+ * their FP32 sigmas.  ps_block caps the P-space block (n_guess) of that
+ * shape in plans of that precision (-1: n_guess itself; 0: no block);
+ * e_waves sets the number of waves of the 512-thread workgroup that
+ * contract the pair matrix in sigmas of that precision, each into its own
+ * LDS slice (0: as many as LDS holds; a larger request is lowered to what
+ * fits).  Neither changes the converged
+ * result beyond rounding: ps_block changes the starting vector and the
+ * preconditioner, e_waves the order of the sigma's column work.  Values
+ * come from a tuner that times the solver on the caller's workload
+ * (paper_2307_10675_amd/tune.py); a plan starts with every entry at its
+ * built-in choice.  IFCI_ERR_ARG outside k 1..8, ps_block -1..64,
+ * e_waves 0..8. */
+ifci_status ifci_set_tuning(ifci_plan_t plan, int32_t k, int32_t precision, int32_t ps_block, int32_t e_waves);
+
 const char* ifci_status_string(ifci_status s);
 const char* ifci_last_error(void);
 

@@ -425,6 +425,7 @@ ifci_status launch_on_chip(ifci_plan_s* p, const std::vector<int32_t>& ids, int6
   A.evict = evict_mask;
   A.e_const = p->e_const;
   A.phase = p->phase_counters;
+  A.tune = p->tune;
   HIP_TRY(launch_batched(A, batch_lds(p, ids), st), "ifci_davidson batched");
   return IFCI_OK;
 }
@@ -880,6 +881,19 @@ ifci_status ifci_set_phase_counters(ifci_plan_t p, int64_t* counters, int64_t n)
     return IFCI_ERR_ARG;
   }
   p->phase_counters = counters;
+  return IFCI_OK;
+}
+
+ifci_status ifci_set_tuning(ifci_plan_t p, int32_t k, int32_t precision, int32_t ps_block, int32_t e_waves) {
+  if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
+  if (k < 1 || k > ifci::kTuneK || (precision != IFCI_FP64 && precision != IFCI_MIXED) || ps_block < -1 ||
+      ps_block > ifci::kPsMax || e_waves < 0 || e_waves > kBatchThreads / 64) {
+    set_error("ifci_set_tuning: k 1..8, precision FP64 or MIXED, ps_block -1..64, e_waves 0..8");
+    return IFCI_ERR_ARG;
+  }
+  const int pr = precision == IFCI_MIXED ? 1 : 0;
+  p->tune.ps_block[k][pr] = (int8_t)ps_block;
+  p->tune.e_waves[k][pr] = (int8_t)e_waves;
   return IFCI_OK;
 }
 

@@ -664,6 +664,9 @@ __device__ inline int et_waves_for(const IncDev& d, const Lds& L) {
   return w > nw ? nw : w;
 }
 
+// The tuned number of contracting waves, never above what LDS holds.
+__device__ __forceinline__ int tuned_waves(int fit, int tuned) { return tuned > 0 && tuned < fit ? tuned : fit; }
+
 // Load the increment's tables and diagonal data and write the diagonal to HD.
 __device__ inline void load_increment(const IncDev& d, const Lds& L, const int32_t* __restrict__ tables,
                                       const double* __restrict__ B, double* __restrict__ HD) {
@@ -1128,7 +1131,10 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
   // P-space block: initial vector and block preconditioner (or the lowest
   // determinant and the diagonal preconditioner)
   float* Ug = (float*)(base + ps_image_offset(st, mmax));
-  const int P = A.n_guess > 1 ? ps_size<K>(d, L, A.n_guess) : 0;
+  // P-space block: n_guess, capped per shape by the tuning table
+  const int tp = A.tune.ps_block[K][A.precision == IFCI_MIXED ? 1 : 0];
+  const int ng = tp >= 0 && tp < A.n_guess ? tp : A.n_guess;
+  const int P = ng > 1 ? ps_size<K>(d, L, ng) : 0;
   float* Us = (float*)(L.et + ps_scratch_offset(d));
   double* zP = L.Gs;
   if (P > 0) {
@@ -1149,8 +1155,8 @@ __device__ __forceinline__ void solve_lobpcg(const SolveArgs& A, int pos, char* 
 
   // every vector of the increment addressed from `base` by a 32-bit offset
   const int nsi = (int)ns, sti = (int)st, mst = mmax * (int)st;
-  const int ew64 = et_waves_for<double, K>(d, L);
-  const int ew32 = et_waves_for<float, K>(d, L);
+  const int ew64 = tuned_waves(et_waves_for<double, K>(d, L), A.tune.e_waves[K][0]);
+  const int ew32 = tuned_waves(et_waves_for<float, K>(d, L), A.tune.e_waves[K][1]);
   int phase = (A.precision == IFCI_MIXED) ? 32 : 64;
   int iters = 0, status = IFCI_INC_NOT_CONVERGED;
   double theta = 0.0, resid = 1e300;
@@ -1488,7 +1494,10 @@ __device__ __forceinline__ void solve_dav(const SolveArgs& A, int pos, char* lds
   constexpr int NE = (max_strings(K) * (max_strings(K) + 1) / 2 + kBatchThreads - 1) / kBatchThreads;
   int bsp = 0;
   float* Ug = (float*)(base + ps_image_offset(st, mmax));
-  const int P = A.n_guess > 1 ? ps_size<K>(d, L, A.n_guess) : 0;
+  // P-space block: n_guess, capped per shape by the tuning table
+  const int tp = A.tune.ps_block[K][A.precision == IFCI_MIXED ? 1 : 0];
+  const int ng = tp >= 0 && tp < A.n_guess ? tp : A.n_guess;
+  const int P = ng > 1 ? ps_size<K>(d, L, ng) : 0;
   float* Us = (float*)(L.et + ps_scratch_offset(d));
   if (P > 0) {
     uint64_t pk;
@@ -1509,8 +1518,8 @@ __device__ __forceinline__ void solve_dav(const SolveArgs& A, int pos, char* lds
 
   const int nsi = (int)ns, sti = (int)st, mst = mmax * (int)st;
   const int lane = tid & 63, wave = tid >> 6, nw = kBatchThreads >> 6;
-  const int ew64 = et_waves_for<double, K>(d, L);
-  const int ew32 = et_waves_for<float, K>(d, L);
+  const int ew64 = tuned_waves(et_waves_for<double, K>(d, L), A.tune.e_waves[K][0]);
+  const int ew32 = tuned_waves(et_waves_for<float, K>(d, L), A.tune.e_waves[K][1]);
   int phase = (A.precision == IFCI_MIXED) ? 32 : 64;
   int m = 0, iters = 0, status = IFCI_INC_NOT_CONVERGED;
   double theta = 0.0, resid = 1e300;

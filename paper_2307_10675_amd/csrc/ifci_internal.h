@@ -72,6 +72,15 @@ __host__ __device__ inline int64_t ps_image_offset(int64_t stride, int mmax) {
   return (2 * (int64_t)mmax + 2) * stride;
 }
 
+// Per-shape settings of the on-chip solvers (k = active orbitals 1..8,
+// precision 0 = FP64 sigma, 1 = FP32 sigma), chosen by a tuner and handed
+// over through ifci_set_tuning; -1 / 0 keep the built-in choice.
+constexpr int kTuneK = 8;
+struct Tuning {
+  int8_t ps_block[kTuneK + 1][2];  // P-space block size (-1: n_guess)
+  int8_t e_waves[kTuneK + 1][2];   // waves contracting E slices (0: all that fit)
+};
+
 struct SolveArgs {
   const IncDev* inc;
   const int32_t* order;   // which increments, heaviest first
@@ -94,6 +103,7 @@ struct SolveArgs {
   const uint8_t* evict;
   double e_const;
   int64_t* phase;   // optional [n_inc][kPhases] clock counters (tracing)
+  Tuning tune;
 };
 
 // Phases recorded by the tracing counters of the batched solver.

@@ -176,6 +176,8 @@ ifci_status plan_build(ifci_plan_s* P, const ifci_problem* pr, const ifci_option
   P->order = pr->order;
   P->e_const = pr->e_const;
   P->opt = *op;
+  std::memset(P->tune.ps_block, -1, sizeof(P->tune.ps_block));
+  std::memset(P->tune.e_waves, 0, sizeof(P->tune.e_waves));
   if (op->max_space < 2 || op->max_space > kMaxSpace || op->max_iter < 1 || !(op->r_tol > 0) ||
       (op->precision != IFCI_FP64 && op->precision != IFCI_MIXED) ||
       (op->solver != IFCI_SOLVER_BATCHED && op->solver != IFCI_SOLVER_PLAIN) || op->n_guess < 0 ||

@@ -19,6 +19,7 @@ struct ifci_plan_s {
   std::vector<std::vector<int>> bodies;
   std::vector<int> nocc;
   ifci_options opt{};
+  ifci::Tuning tune;  // per-shape settings of the on-chip solvers (ifci_set_tuning)
   // increments
   std::vector<std::vector<int>> inc_bodies;
   std::vector<ifci::IncDev> inc;

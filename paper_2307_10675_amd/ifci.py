@@ -75,6 +75,8 @@ _SIGNATURES = {
     "ifci_rdm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.c_void_p]),
     "ifci_set_phase_counters": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
+    "ifci_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32]),
     "ifci_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ifci_last_error": (ctypes.c_char_p, []),
 }
@@ -119,6 +121,24 @@ def default_options(**kw) -> Options:
     return o
 
 
+TUNING_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+
+
+def load_tuning(path: str = TUNING_PATH):
+    """{(k, precision): (ps_block, e_waves)} from the tuner's cache
+    (paper_2307_10675_amd/tune.py), or {} when there is none."""
+    import json
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except OSError:
+        return {}
+    out = {}
+    for e in d.get("entries", []):
+        out[(int(e["k"]), int(e["precision"]))] = (int(e["ps_block"]), int(e["e_waves"]))
+    return out
+
+
 def tables(k: int, n_alpha: int):
     """(strings, link[n_str][n_link][4]) of a (k, n_alpha) space, host only."""
     from math import comb
@@ -143,7 +163,10 @@ class Plan:
     and order (and optionally e_const) -- e.g. synthetic.Problem; the
     integrals come with attach()."""
 
-    def __init__(self, problem, precision=FP64, solver=BATCHED, device: int = 0, **opts):
+    def __init__(self, problem, precision=FP64, solver=BATCHED, device: int = 0, tuning="cache", **opts):
+        """tuning: "cache" applies the committed tuner results (tuning.json,
+        when present), None keeps the built-in choices, or a dict
+        {(k, precision): (ps_block, e_waves)}."""
         self._keep = []
         bodies = [list(b) for b in problem.bodies]
         ptr = np.cumsum([0] + [len(b) for b in bodies]).astype(np.int32)
@@ -161,6 +184,10 @@ class Plan:
         _check(lib().ifci_plan_create(ctypes.byref(pr), ctypes.byref(self.options), device, ctypes.byref(h)))
         self._h = h
         self.device = device
+        if tuning == "cache":
+            tuning = load_tuning()
+        for (k, prec), (ps, ew) in (tuning or {}).items():
+            self.set_tuning(k, prec, ps, ew)
         self.order = problem.order
         self.n_orb = n_orb
         self.workspace = None
@@ -251,6 +278,10 @@ class Plan:
         _check(lib().ifci_davidson(self._h, first, count, _ptr(e), _ptr(st), _ptr(ev), _ptr(it), _ptr(rs),
                                    _stream(stream)))
         return e, st, it, rs
+
+    def set_tuning(self, k: int, precision: int, ps_block: int = -1, e_waves: int = 0):
+        """Per-shape settings of the on-chip solvers (ifci_set_tuning)."""
+        _check(lib().ifci_set_tuning(self._h, int(k), int(precision), int(ps_block), int(e_waves)))
 
     def trace_phases(self, enable: bool = True):
         """Per-increment phase clock counters of the batched solver (int64

@@ -1,0 +1,132 @@
+"""Tuner of the on-chip increment solvers.
+
+For each plan precision and each increment shape of a workload (k active
+orbitals, at most 8; the largest shape first) it tries every candidate
+setting of ifci_set_tuning -- the P-space block size and the number of
+waves that contract the pair matrix -- with the other shapes at their
+current choice, and keeps the one that gives the shortest launch over the
+whole workload (the quantity the benchmark measures: the shapes share one
+launch, so a shape's own time matters only where it shows at the end)
+among those whose increments all converge; the time of that shape's
+increments alone is recorded beside it.  The FP64 plan is tuned first; its
+wave counts then also serve the FP64 refinement sigmas of the mixed plan.
+The result is a JSON cache (paper_2307_10675_amd/tuning.json) that Plan
+applies at creation.
+
+    python -m paper_2307_10675_amd.tune [--workload 2] [--out tuning.json]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PS_CHOICES = (0, 16, 32, 48, 64)
+WAVE_CHOICES = (0, 2, 4, 6)
+
+
+def shape_ranges(plan):
+    """{k: (first, count)}: the longest contiguous run of increments of each
+    on-chip shape (k active orbitals) in the plan's order."""
+    incs = plan.increments()
+    runs = {}
+    i = 0
+    while i < len(incs):
+        j = i
+        while j < len(incs) and incs[j].n_act == incs[i].n_act and incs[j].n_alpha == incs[i].n_alpha:
+            j += 1
+        k = incs[i].n_act
+        if k <= 8 and (k not in runs or j - i > runs[k][1]):
+            runs[k] = (i, j - i)
+        i = j
+    return runs
+
+
+def time_range(plan, first, count, reps, torch):
+    """Median launch time (ms, HIP events on the current stream) of the
+    solver over [first, first + count), and whether every increment converged."""
+    from paper_2307_10675_amd import ifci
+    times, ok = [], True
+    for r in range(reps + 1):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        e, st, it, rs = plan.davidson(first, count)
+        b.record()
+        torch.cuda.synchronize()
+        if r > 0:
+            times.append(a.elapsed_time(b))
+        ok = ok and bool((st.cpu().numpy() == ifci.INC_DONE).all())
+    times.sort()
+    return times[len(times) // 2], ok
+
+
+def tune(problem, h, eri, max_space=3, r_tol=1e-5, r_tol_inner=1e-5, reps=3, log=print):
+    import torch
+
+    from paper_2307_10675_amd import ifci
+    entries = []
+    fp64_waves = {}
+    for precision in (ifci.FP64, ifci.MIXED):
+        plan = ifci.Plan(problem, precision=precision, max_space=max_space, r_tol=r_tol,
+                         r_tol_inner=r_tol_inner, max_iter=600, tuning=None).attach(h, eri)
+        if precision == ifci.MIXED:
+            for k, ew in fp64_waves.items():
+                plan.set_tuning(k, ifci.FP64, -1, ew)
+        n_inc = plan.n_inc
+        default_all, _ = time_range(plan, 0, n_inc, reps, torch)
+        for k, (first, count) in sorted(shape_ranges(plan).items(), reverse=True):
+            if k < 2:
+                continue
+            plan.set_tuning(k, precision, -1, 0)
+            default_ms, _ = time_range(plan, first, count, reps, torch)
+            results = []
+            for ps in PS_CHOICES:
+                for ew in WAVE_CHOICES:
+                    plan.set_tuning(k, precision, ps, ew)
+                    ms, ok = time_range(plan, 0, n_inc, reps, torch)
+                    results.append((ms, ps, ew, ok))
+                    log(f"k={k} precision={precision} ps_block={ps} e_waves={ew}: whole launch {ms:.3f} ms"
+                        f"{'' if ok else ' (not converged)'}")
+            ms, ps, ew, _ = min(r for r in results if r[3])
+            plan.set_tuning(k, precision, ps, ew)
+            shape_ms, _ = time_range(plan, first, count, reps, torch)
+            if precision == ifci.FP64:
+                fp64_waves[k] = ew
+            entries.append(dict(k=k, precision=precision, ps_block=ps, e_waves=ew, launch_ms=ms,
+                                default_launch_ms=default_all, shape_ms=shape_ms, default_shape_ms=default_ms,
+                                increments=count))
+        plan.close()
+    return entries
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--max-space", type=int, default=3)
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--out", default=os.path.join(HERE, "tuning.json"))
+    a = ap.parse_args()
+    sys.path.insert(0, os.path.dirname(HERE))
+    import torch
+
+    from paper_2307_10675_amd import synthetic
+    problem = synthetic.workload(a.workload)
+    dev = torch.device("cuda", 0)
+    h = torch.tensor(problem.h, dtype=torch.float64, device=dev)
+    eri = torch.tensor(problem.eri, dtype=torch.float64, device=dev).contiguous()
+    t0 = time.time()
+    entries = tune(problem, h, eri, max_space=a.max_space, reps=a.reps, log=lambda s: print(s, flush=True))
+    out = dict(device=torch.cuda.get_device_properties(0).gcnArchName.split(":")[0],
+               workload=f"synthetic workload {a.workload}", max_space=a.max_space,
+               seconds=round(time.time() - t0, 1), entries=entries)
+    with open(a.out, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+if __name__ == "__main__":
+    main()

@@ -135,3 +135,28 @@ def test_davidson_group_argument_errors(L):
     assert L.ifci_davidson_group(same, 2, outs, outs, None, None, None) == 1  # listed twice
     one = (ctypes.c_void_p * 1)(a._h.value)
     assert L.ifci_davidson_group(one, 1, outs, outs, None, None, None) == 6   # no workspace
+
+
+def test_set_tuning_arguments(L, tmp_path):
+    """ifci_set_tuning takes k 1..8, FP64 or MIXED, ps_block -1..64 and
+    e_waves 0..8; the tuner cache round-trips through load_tuning."""
+    import json
+    from paper_2307_10675_amd import ifci, synthetic
+    p = synthetic.single(4, 12, 1)
+    a = ifci.Plan(p, tuning=None)
+    h = a._h
+    assert L.ifci_set_tuning(h, 8, ifci.MIXED, 64, 0) == 0
+    assert L.ifci_set_tuning(h, 1, ifci.FP64, -1, 8) == 0
+    for k, pr, ps, ew in ((0, 0, 0, 0), (9, 0, 0, 0), (4, 2, 0, 0), (4, 0, -2, 0), (4, 0, 65, 0), (4, 0, 0, 9),
+                          (4, 0, 0, -1)):
+        assert L.ifci_set_tuning(h, k, pr, ps, ew) == 1
+    assert L.ifci_set_tuning(None, 4, 0, 0, 0) == 1
+    f = tmp_path / "t.json"
+    f.write_text(json.dumps({"entries": [{"k": 8, "precision": 1, "ps_block": 48, "e_waves": 6},
+                                         {"k": 6, "precision": 0, "ps_block": 0, "e_waves": 0}]}))
+    t = ifci.load_tuning(str(f))
+    assert t == {(8, 1): (48, 6), (6, 0): (0, 0)}
+    assert ifci.load_tuning(str(tmp_path / "missing.json")) == {}
+    b = ifci.Plan(p, tuning=t)
+    b.close()
+    a.close()
