@@ -105,16 +105,18 @@ typedef struct {
                          three-vector {x, w, p} iteration (locally
                          optimal, no restarts) */
   uint32_t flags;     /* IFCI_FLAG_* bits */
-  int32_t n_guess;    /* three-vector on-chip solver (max_space 3): the
-                         n_guess (at most 64, rounded down to even) lowest
-                         diagonal entries of the symmetric sector span a
-                         block of H that is diagonalised once per
+  int32_t n_guess;    /* on-chip solvers (increments of up to 8 active
+                         orbitals): the n_guess lowest diagonal entries of
+                         the symmetric sector (rounded down to even, at most
+                         64 and an eighth of the sector) span a block of H
+                         (Slater-Condon rules) that is diagonalised once per
                          increment; its lowest eigenvector is the initial
-                         guess and its exact inverse the preconditioner on
-                         those entries (a block Davidson preconditioner).
-                         0 or 1: the single lowest determinant and the
-                         diagonal preconditioner.  The other solvers use
-                         the latter in any case. */
+                         guess and its shifted inverse (theta - H_PP)^-1 the
+                         preconditioner on those entries, the diagonal one
+                         elsewhere (a block Davidson preconditioner).  0 or
+                         1: the single lowest determinant and the diagonal
+                         preconditioner.  The device-wide solver (above 8
+                         orbitals) uses the latter in any case. */
 } ifci_options;
 
 /* ifci_davidson returns as soon as the work of every increment is

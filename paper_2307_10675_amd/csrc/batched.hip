@@ -873,14 +873,19 @@ __device__ inline int64_t ps_scratch_bytes(int P, int K) {
   return 8LL * P * P + 1024 + 8LL * (2 * K * K + np * np) + 64;
 }
 
-// Block size for this increment: even, at most n_guess, kPsMax and the
-// sector dimension, with room in LDS for the set-up (A, U, h', the
-// rotations) and, across iterations, for the FP32 U image below the
-// diagonal-pair weights of both precisions.
+// Block size for this increment: even, at most n_guess, kPsMax and an
+// eighth of the sector dimension, with room in LDS for the set-up (A, U,
+// h', the rotations) and, across iterations, for the FP32 U image below the
+// diagonal-pair weights of both precisions.  The eighth: a block that
+// covers most of the sector makes the preconditioner nearly the exact
+// shifted inverse, whose correction is nearly parallel to the vector
+// itself, and an iteration started from the block's lowest eigenvector can
+// then settle on an excited state next to it (seen in mixed precision on a
+// 4o4e increment, 20 of 21 entries in the block).
 template <int K>
 __device__ inline int ps_size(const IncDev& d, const Lds& L, int n_guess) {
   int P = n_guess < kPsMax ? n_guess : kPsMax;
-  if (P > (int)d.n_sym) P = (int)d.n_sym;
+  if (P > (int)d.n_sym / 8) P = (int)d.n_sym / 8;
   P &= ~1;
   const int64_t off = ps_scratch_offset(d);
   const int64_t wt = wt_offset(L, K, 4) < wt_offset(L, K, 8) ? wt_offset(L, K, 4) : wt_offset(L, K, 8);

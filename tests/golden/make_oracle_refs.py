@@ -57,9 +57,11 @@ def _densities(args):
     return S, rdm.increment_densities(problem, S)
 
 
-def dump_gradient(name, problem, jobs):
+def dump_gradient(name, problem, jobs, n_sample=4096, seed=3):
     """Every increment energy of the expansion and its gradient (weighted
-    1- and 2-particle densities) from the oracle, in increment order."""
+    1- and 2-particle densities) from the oracle, in increment order: the
+    whole dE/dh and a seeded sample of dE/d(pq|rs) entries (with the
+    Frobenius norm of the whole array), as JSON."""
     t = time.time()
     subsets = ifci.increments(problem.n_bodies, problem.order)
     E, gap = {}, {}
@@ -73,16 +75,19 @@ def dump_gradient(name, problem, jobs):
         e_tot, dh, deri = rdm.accumulate_gradient(problem, stream(ex))
     e_ref = ifci.reference_energy(problem)
     eps, by_order, total = ifci.increments_from_energies(E, e_ref, problem.order)
-    npz = os.path.join(HERE, f"oracle_{name}_grad.npz")
-    np.savez_compressed(npz, e_total=np.array(e_tot), dE_dh=dh, dE_deri=deri)
+    idx = np.random.default_rng(seed).choice(deri.size, size=min(n_sample, deri.size), replace=False)
+    idx.sort()
+    grad = dict(e_total=float(e_tot), dE_dh=[float(x) for x in dh.ravel()],
+                dE_deri_index=[int(i) for i in idx], dE_deri_value=[float(x) for x in deri.ravel()[idx]],
+                dE_deri_norm=float(np.linalg.norm(deri)))
     doc = dict(problem=problem.meta, sha256=problem.sha256(), order=problem.order, e_ref=e_ref,
                increments=[dict(bodies=list(S), E=E[S], gap=gap[S]) for S in subsets],
                eps=[eps[S] for S in subsets], by_order=by_order, total=total,
-               gradient=dict(file=os.path.basename(npz), e_total=e_tot), seconds=time.time() - t)
+               gradient=grad, seconds=time.time() - t)
     path = os.path.join(HERE, f"oracle_{name}.json")
     with open(path, "w") as f:
-        json.dump(doc, f, indent=1)
-    print(f"{name}: {len(subsets)} increments and the gradient in {doc['seconds']:.1f} s -> {path}, {npz}")
+        json.dump(doc, f)
+    print(f"{name}: {len(subsets)} increments and the gradient in {doc['seconds']:.1f} s -> {path}")
 
 
 def dump(name, problem, subsets, jobs, full_expansion, checkpoint=None):

@@ -142,20 +142,27 @@ def test_full_order_six_bodies_three_vector_option():
 
 
 def test_solve_sixteen_orbitals():
-    """16o16e FCI (165,636,900 determinants) in mixed precision on the
-    device-wide path (split column sigma): converged, below the reference
-    energy, and the oracle's Slater-Condon rows of H c - E c on 16 sampled
-    determinants within the residual-norm bound."""
+    """16o16e FCI (165,636,900 determinants) on the device-wide path (split
+    column sigma), in mixed precision and in FP64: both converged, below the
+    reference energy, within 1e-6 of each other, and the oracle's
+    Slater-Condon rows of H c - E c on 16 sampled determinants within the
+    residual-norm bound for each."""
     import torch
-    print("[large] solve 16o16e", flush=True)
     p = synthetic.single(16, 32, 4016)
-    plan, res = ifci.solve(p, precision=ifci.MIXED, r_tol=3e-5, r_tol_inner=1e-5, max_iter=400)
-    torch.cuda.synchronize()
-    assert int(res["status"][0]) == ifci.INC_DONE
-    E = float(res["E"][0])
-    assert E < oifci.reference_energy(p)
-    c = plan.vector(0).cpu().numpy()
-    assert abs(np.linalg.norm(c) - 1.0) < 1e-9
-    rows = _rows(len(c), 16016, count=16)
-    r = certify.sigma_rows_strings(rows, 8, c, p.h, p.eri) - E * c[rows]
-    assert np.abs(r).max() <= 3e-5
+    E = {}
+    for name, prec in (("mixed", ifci.MIXED), ("fp64", ifci.FP64)):
+        print(f"[large] solve 16o16e {name}", flush=True)
+        plan, res = ifci.solve(p, precision=prec, r_tol=1e-5, r_tol_inner=1e-5, max_iter=400)
+        torch.cuda.synchronize()
+        assert int(res["status"][0]) == ifci.INC_DONE
+        E[name] = float(res["E"][0])
+        assert E[name] < oifci.reference_energy(p)
+        c = plan.vector(0).cpu().numpy()
+        assert abs(np.linalg.norm(c) - 1.0) < 1e-9
+        rows = _rows(len(c), 16016, count=16)
+        r = certify.sigma_rows_strings(rows, 8, c, p.h, p.eri) - E[name] * c[rows]
+        assert np.abs(r).max() <= 1e-5
+        plan.close()
+        del plan, res, c
+        torch.cuda.empty_cache()
+    assert abs(E["mixed"] - E["fp64"]) <= 1e-6
