@@ -79,7 +79,8 @@ enum {
   IFCI_INC_PENDING = 0,
   IFCI_INC_DONE = 1,
   IFCI_INC_NOT_CONVERGED = 2,
-  IFCI_INC_EVICTED = 3
+  IFCI_INC_EVICTED = 3,
+  IFCI_INC_SCREENED = 4  /* dropped by ifci_screen: not solved, energy NaN */
 };
 
 /* The problem (paper, Methods: eqs. 1-5 and the reference determinant). */
@@ -254,10 +255,30 @@ ifci_status ifci_davidson(ifci_plan_t plan, int64_t first, int64_t count, double
  * increment count, as in ifci_davidson; iters_out and resid_out may be NULL.
  * Stream order and return as in ifci_davidson; converged vectors stay in
  * each plan's workspace.  The first plan keeps the solve's control block
- * (device memory it allocates on first use and grows as needed). */
+ * (device memory it allocates on first use and grows as needed).
+ * IFCI_ERR_UNSUPPORTED for a plan with a screening mask (ifci_screen). */
 ifci_status ifci_davidson_group(const ifci_plan_t* plans, int32_t n_plans, double* const* e_out,
                                 int32_t* const* status_out, int32_t* const* iters_out,
                                 double* const* resid_out, ifci_stream_t stream);
+
+/* Connected n-body screening (paper, Methods, iFCI subsection, the CnB
+ * paragraph; the criterion's details are in the paper's Supplementary
+ * Information, which is not available -- this is the reading taken).  From
+ * the total energies of every increment of one and two bodies (e_inc, device
+ * [n_inc], increment order; the entries of larger increments are not read):
+ * bodies i and j are connected when |eps_ij| >= threshold (eq. 3); an
+ * increment of three or more bodies is kept when its bodies form one
+ * connected graph under that relation; increments of one or two bodies are
+ * always kept.  The mask stays with the plan: ifci_davidson then skips
+ * dropped increments (status IFCI_INC_SCREENED, energy NaN, no work),
+ * ifci_energy sums the screened expansion, and ifci_rdm (weights NULL)
+ * weights each kept increment's densities by its coefficient in that sum
+ * (user weights must be zero on dropped increments).  keep (host [n_inc],
+ * may be NULL) receives the mask, n_kept (may be NULL) its count.
+ * threshold < 0 removes the mask.  Synchronises the stream.  IFCI_ERR_ARG
+ * when a one- or two-body energy is not finite (solve those first). */
+ifci_status ifci_screen(ifci_plan_t plan, const double* e_inc, double threshold, uint8_t* keep,
+                        int64_t* n_kept, ifci_stream_t stream);
 
 /* Copy the converged unit vector of increment inc (device [n_det]). */
 ifci_status ifci_vector(ifci_plan_t plan, int64_t inc, double* c_out, ifci_stream_t stream);
@@ -265,8 +286,12 @@ ifci_status ifci_vector(ifci_plan_t plan, int64_t inc, double* c_out, ifci_strea
 /* Energy assembly, eqs. 2-5: from device e_inc [n_inc] total energies
  * compute eps [n_inc] (device, may be NULL) and host out[order + 2] =
  * {E_total, E_ref, E_c^(1), ..., E_c^(n)}.  Synchronises the stream.
- * status (device [n_inc] or NULL): IFCI_ERR_NOT_CONVERGED if any word is not
- * IFCI_INC_DONE (outputs still written). */
+ * status (device [n_inc] or NULL): IFCI_ERR_NOT_CONVERGED if any word is
+ * neither IFCI_INC_DONE nor IFCI_INC_SCREENED (outputs still written).
+ * With a screening mask (ifci_screen) a dropped increment has eps = 0 and a
+ * kept one eps_S = E_c(S) - sum over proper non-empty subsets of eps_T (the
+ * recursion of eqs. 2-5); without one, the same sums in their closed
+ * inclusion-exclusion form. */
 ifci_status ifci_energy(ifci_plan_t plan, const double* e_inc, const int32_t* status,
                         double* eps, double* out, ifci_stream_t stream);
 

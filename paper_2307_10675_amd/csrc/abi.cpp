@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <cstring>
 #include <map>
@@ -96,6 +97,7 @@ void free_device(ifci_plan_s* P) {
   free_one(P->d_rdm_off);
   free_one(P->d_loc);
   free_one(P->d_w_inc);
+  free_one(P->d_keep);
   free_one(P->group_ctl);
   P->group_ctl_bytes = 0;
   release_in_flight(P, true);
@@ -130,6 +132,7 @@ ifci_status ensure_device(ifci_plan_s* P) {
   if (e == hipSuccess) e = upload(&P->d_rdm_off, P->rdm_off);
   if (e == hipSuccess) e = upload(&P->d_loc, P->h_loc);
   if (e == hipSuccess) e = upload(&P->d_w_inc, P->h_w_inc);
+  if (e == hipSuccess && !P->keep.empty()) e = upload(&P->d_keep, P->keep);
   if (e != hipSuccess) {
     free_device(P);
     return dev_err(e, "uploading plan tables");
@@ -724,13 +727,22 @@ ifci_status ifci_davidson(ifci_plan_t p, int64_t first, int64_t count, double* e
   const bool plain_only = p->opt.solver == IFCI_SOLVER_PLAIN;
   // batched part: heaviest first
   std::vector<int32_t> ids, rest;
+  const bool screened = !p->keep.empty();
+  bool any_dropped = false;
   for (int32_t i : p->order_all)
     if (i >= first && i < first + count) {
+      if (screened && !p->keep[i]) {
+        any_dropped = true;
+        continue;
+      }
       if (!plain_only && p->batched_ok[i])
         ids.push_back(i);
       else
         rest.push_back(i);
     }
+  if (any_dropped)
+    HIP_TRY(launch_mark_screened(p->d_keep, first, count, e_out, status_out, iters_out, resid_out, st),
+            "ifci_davidson screened");
   s = launch_on_chip(p, ids, first, e_out, status_out, evict_mask, iters_out, resid_out, st);
   if (s != IFCI_OK) return s;
   if (!rest.empty() && !plain_only) {
@@ -818,7 +830,7 @@ ifci_status ifci_davidson(ifci_plan_t p, int64_t first, int64_t count, double* e
       for (int w = 0; w < W; ++w) HIP_TRY(hipStreamWaitEvent(st, p->slot_events[w], 0), "ifci_davidson");
     }
   }
-  for (int64_t i = first; i < first + count; ++i) p->solved[i] = 1;
+  for (int64_t i = first; i < first + count; ++i) p->solved[i] = screened ? p->keep[i] : 1;
   return IFCI_OK;
 }
 
@@ -848,6 +860,10 @@ ifci_status ifci_davidson_group(const ifci_plan_t* plans, int32_t n_plans, doubl
         set_error("ifci_davidson_group: a plan is listed twice");
         return IFCI_ERR_ARG;
       }
+    if (!p->keep.empty()) {
+      set_error("ifci_davidson_group: plan " + std::to_string(j) + " carries a screening mask (use ifci_davidson)");
+      return IFCI_ERR_UNSUPPORTED;
+    }
   }
   for (int32_t j = 0; j < n_plans; ++j) {
     ifci_status s = need_ints(plans[j]);
@@ -897,6 +913,117 @@ ifci_status ifci_set_tuning(ifci_plan_t p, int32_t k, int32_t precision, int32_t
   return IFCI_OK;
 }
 
+ifci_status ifci_screen(ifci_plan_t p, const double* e_inc, double threshold, uint8_t* keep, int64_t* n_kept,
+                        ifci_stream_t stream) {
+  if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
+  const int n_inc = (int)p->inc.size();
+  ifci_status s = need_ints(p);
+  if (s != IFCI_OK) return s;
+  DeviceGuard g(p->device);
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<double> w(n_inc);
+  if (threshold < 0.0 || std::isnan(threshold)) {
+    // no screening: the closed-form weights of eqs. 1-5
+    p->keep.clear();
+    for (int i = 0; i < n_inc; ++i) w[i] = p->weights[p->h_inc_size[i] - 1];
+  } else {
+    if (!e_inc) {
+      set_error("ifci_screen: null e_inc");
+      return IFCI_ERR_ARG;
+    }
+    // increments are ordered by size: the one- and two-body ones come first
+    int n12 = 0;
+    while (n12 < n_inc && p->h_inc_size[n12] <= 2) ++n12;
+    std::vector<double> e(n12);
+    double e_ref = 0.0;
+    HIP_TRY(hipMemcpyAsync(e.data(), e_inc, sizeof(double) * n12, hipMemcpyDeviceToHost, st), "ifci_screen");
+    HIP_TRY(hipMemcpyAsync(&e_ref, p->ws_misc(), sizeof(double), hipMemcpyDeviceToHost, st), "ifci_screen");
+    HIP_TRY(hipStreamSynchronize(st), "ifci_screen");
+    for (int i = 0; i < n12; ++i)
+      if (!std::isfinite(e[i])) {
+        set_error("ifci_screen: the energies of the one- and two-body increments are needed (solve them first)");
+        return IFCI_ERR_ARG;
+      }
+    // eps_ij for every pair of bodies (eq. 3)
+    const int nb = p->n_bodies;
+    std::vector<double> e1(nb, 0.0);
+    std::vector<uint8_t> link((size_t)nb * nb, 0);
+    for (int i = 0; i < n12; ++i)
+      if (p->h_inc_size[i] == 1) e1[p->inc_bodies[i][0]] = e[i] - e_ref;
+    for (int i = 0; i < n12; ++i)
+      if (p->h_inc_size[i] == 2) {
+        const int a = p->inc_bodies[i][0], b = p->inc_bodies[i][1];
+        const double eps = (e[i] - e_ref) - e1[a] - e1[b];
+        link[(size_t)a * nb + b] = link[(size_t)b * nb + a] = std::fabs(eps) >= threshold;
+      }
+    // kept: one or two bodies, or a connected graph of bodies
+    p->keep.assign(n_inc, 1);
+    for (int i = n12; i < n_inc; ++i) {
+      const std::vector<int>& S = p->inc_bodies[i];
+      std::vector<uint8_t> seen(S.size(), 0);
+      std::vector<int> todo(1, 0);
+      seen[0] = 1;
+      int reached = 1;
+      while (!todo.empty()) {
+        const int a = todo.back();
+        todo.pop_back();
+        for (size_t b = 0; b < S.size(); ++b)
+          if (!seen[b] && link[(size_t)S[a] * nb + S[b]]) {
+            seen[b] = 1;
+            ++reached;
+            todo.push_back((int)b);
+          }
+      }
+      p->keep[i] = reached == (int)S.size();
+    }
+    // each kept increment's coefficient in the screened sum: eps_S written
+    // as a combination of E_c(T) over the kept T (recursion of eqs. 2-5 with
+    // the dropped increments at zero), summed over S
+    std::vector<std::vector<std::pair<int, double>>> coef(n_inc);
+    std::vector<double> dense(n_inc, 0.0);
+    std::vector<uint8_t> mark(n_inc, 0);
+    for (int i = 0; i < n_inc; ++i) {
+      if (!p->keep[i]) continue;
+      std::vector<int> touched(1, i);
+      dense[i] = 1.0;
+      mark[i] = 1;
+      for (int t = p->h_sub_ptr[i]; t < p->h_sub_ptr[i + 1]; ++t) {
+        const int T = p->h_sub_idx[t];
+        if (T == i || !p->keep[T]) continue;
+        for (const auto& uv : coef[T]) {
+          if (!mark[uv.first]) {
+            mark[uv.first] = 1;
+            touched.push_back(uv.first);
+          }
+          dense[uv.first] -= uv.second;
+        }
+      }
+      for (int u : touched) {
+        if (dense[u] != 0.0) coef[i].push_back({u, dense[u]});
+        dense[u] = 0.0;
+        mark[u] = 0;
+      }
+    }
+    std::fill(w.begin(), w.end(), 0.0);
+    for (int i = 0; i < n_inc; ++i)
+      for (const auto& uv : coef[i]) w[uv.first] += uv.second;
+    free_one(p->d_keep);
+    HIP_TRY(upload(&p->d_keep, p->keep), "ifci_screen");
+  }
+  p->h_w_inc = w;
+  HIP_TRY(hipMemcpyAsync(p->d_w_inc, p->h_w_inc.data(), sizeof(double) * n_inc, hipMemcpyHostToDevice, st),
+          "ifci_screen");
+  HIP_TRY(hipStreamSynchronize(st), "ifci_screen");
+  int64_t kept = 0;
+  for (int i = 0; i < n_inc; ++i) {
+    const uint8_t k = p->keep.empty() ? 1 : p->keep[i];
+    kept += k;
+    if (keep) keep[i] = k;
+  }
+  if (n_kept) *n_kept = kept;
+  return IFCI_OK;
+}
+
 ifci_status ifci_vector(ifci_plan_t p, int64_t inc, double* c_out, ifci_stream_t stream) {
   if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
   if (inc < 0 || inc >= (int64_t)p->inc.size() || !c_out) {
@@ -930,9 +1057,14 @@ ifci_status ifci_energy(ifci_plan_t p, const double* e_inc, const int32_t* statu
   double* misc = p->ws_misc();
   double* dout = misc + 8;
   int32_t* bad = (int32_t*)(misc + 200);
-  HIP_TRY(launch_energy(e_inc, status, p->d_sub_ptr, p->d_sub_idx, p->d_inc_size, (int)p->inc.size(), p->order,
-                        misc, eps ? eps : p->ws_eps(), dout, bad, st),
-          "ifci_energy");
+  if (p->keep.empty())
+    HIP_TRY(launch_energy(e_inc, status, p->d_sub_ptr, p->d_sub_idx, p->d_inc_size, (int)p->inc.size(), p->order,
+                          misc, eps ? eps : p->ws_eps(), dout, bad, st),
+            "ifci_energy");
+  else
+    HIP_TRY(launch_energy_screened(e_inc, status, p->d_sub_ptr, p->d_sub_idx, p->d_inc_size, p->d_keep,
+                                   (int)p->inc.size(), p->order, misc, eps ? eps : p->ws_eps(), dout, bad, st),
+            "ifci_energy");
   int32_t nbad = 0;
   HIP_TRY(hipMemcpyAsync(out, dout, sizeof(double) * (p->order + 2), hipMemcpyDeviceToHost, st), "ifci_energy");
   HIP_TRY(hipMemcpyAsync(&nbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st), "ifci_energy");
@@ -952,15 +1084,15 @@ ifci_status ifci_rdm(ifci_plan_t p, const double* weights, double* dE_dh, double
   }
   ifci_status s = need_ints(p);
   if (s != IFCI_OK) return s;
-  for (uint8_t v : p->solved)
-    if (!v) {
+  for (size_t i = 0; i < p->solved.size(); ++i)
+    if (!p->solved[i] && (p->keep.empty() || p->keep[i])) {
       set_error("ifci_rdm: every increment must be solved first (ifci_davidson)");
       return IFCI_ERR_STATE;
     }
   DeviceGuard g(p->device);
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(launch_rdm(p->d_inc, p->inc.data(), (int)p->inc.size(), p->ws_dav(), p->d_tables, p->ws_rdm(),
-                     p->d_rdm_off, p->opt.max_space, st),
+                     p->d_rdm_off, p->opt.max_space, p->keep.empty() ? nullptr : p->d_keep, st),
           "ifci_rdm");
   HIP_TRY(launch_rdm_accumulate(p->d_inc, (int)p->inc.size(), p->d_orbs, (const int32_t*)p->d_loc, p->ws_rdm(),
                                 p->d_rdm_off, weights ? weights : p->d_w_inc, p->d_orbs + p->ref_off,

@@ -1,4 +1,5 @@
-// Energy assembly of the incremental expansion (paper, iFCI section, eqs. 1-5).
+// Energy assembly of the incremental expansion (paper, iFCI section, eqs. 1-5),
+// with or without connected n-body screening (the CnB paragraph).
 //
 // eqs. 2-5 define eps_S = E_c(S) - sum over proper non-empty subsets T of
 // eps_T.  Unrolling that recursion gives the equivalent closed form
@@ -101,7 +102,7 @@ __global__ void __launch_bounds__(kSumThreads)
   }
   int nb = 0;
   if (status)
-    for (int i = t; i < n_inc; i += kSumThreads) nb += (status[i] != IFCI_INC_DONE);
+    for (int i = t; i < n_inc; i += kSumThreads) nb += (status[i] != IFCI_INC_DONE && status[i] != IFCI_INC_SCREENED);
   sb[t] = nb;
   __syncthreads();
   for (int w = kSumThreads / 2; w > 0; w >>= 1) {
@@ -113,6 +114,60 @@ __global__ void __launch_bounds__(kSumThreads)
     out[1] = misc[0];
     *bad = sb[0];
   }
+}
+
+// Screened expansion, one size level at a time (levels ascending): a kept
+// increment's eps_S = E_c(S) - sum over its proper subsets of eps_T (the
+// dropped ones hold 0), a dropped one's eps_S = 0.
+__global__ void eps_screened_kernel(const double* __restrict__ e_inc, const int32_t* __restrict__ sub_ptr,
+                                    const int32_t* __restrict__ sub_idx, const int32_t* __restrict__ inc_size,
+                                    const uint8_t* __restrict__ keep, int n_inc, int level,
+                                    const double* __restrict__ misc, double* __restrict__ eps) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inc || inc_size[i] != level) return;
+  if (!keep[i]) {
+    eps[i] = 0.0;
+    return;
+  }
+  Neumaier acc;
+  acc.add(e_inc[i] - misc[0]);
+  for (int t = sub_ptr[i]; t < sub_ptr[i + 1]; ++t) {
+    const int T = sub_idx[t];
+    if (T != i) acc.add(-eps[T]);
+  }
+  eps[i] = acc.value();
+}
+
+hipError_t launch_energy_screened(const double* e_inc, const int32_t* status, const int32_t* sub_ptr,
+                                  const int32_t* sub_idx, const int32_t* inc_size, const uint8_t* keep, int n_inc,
+                                  int order, const double* misc_in, double* eps, double* out, int32_t* bad,
+                                  hipStream_t st) {
+  for (int level = 1; level <= order; ++level)
+    hipLaunchKernelGGL(eps_screened_kernel, dim3((n_inc + 255) / 256), dim3(256), 0, st, e_inc, sub_ptr, sub_idx,
+                       inc_size, keep, n_inc, level, misc_in, eps);
+  hipLaunchKernelGGL(order_sum_kernel, dim3(1), dim3(kSumThreads), 0, st, eps, inc_size, n_inc, order, misc_in,
+                     status, out, bad);
+  return hipGetLastError();
+}
+
+// Outputs of the dropped increments of [first, first + count): energy and
+// residual NaN, status IFCI_INC_SCREENED, no iterations.
+__global__ void mark_screened_kernel(const uint8_t* __restrict__ keep, int64_t first, int64_t count,
+                                     double* __restrict__ e_out, int32_t* __restrict__ status_out,
+                                     int32_t* __restrict__ iters_out, double* __restrict__ resid_out) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= count || keep[first + o]) return;
+  e_out[o] = __builtin_nan("");
+  status_out[o] = IFCI_INC_SCREENED;
+  if (iters_out) iters_out[o] = 0;
+  if (resid_out) resid_out[o] = __builtin_nan("");
+}
+
+hipError_t launch_mark_screened(const uint8_t* keep, int64_t first, int64_t count, double* e_out,
+                                int32_t* status_out, int32_t* iters_out, double* resid_out, hipStream_t st) {
+  hipLaunchKernelGGL(mark_screened_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, keep, first,
+                     count, e_out, status_out, iters_out, resid_out);
+  return hipGetLastError();
 }
 
 hipError_t launch_energy(const double* e_inc, const int32_t* status, const int32_t* sub_ptr,

@@ -105,13 +105,19 @@ hipError_t wide_iteration(const WideRun& R, hipStream_t s);  // one iteration's 
 hipError_t wide_finish(WideItem* const* items, int n, const int32_t* out_pos, double e_const, double* e_out,
                        int32_t* status_out, int32_t* iters_out, double* resid_out, hipStream_t s);
 
+hipError_t launch_energy_screened(const double* e_inc, const int32_t* status, const int32_t* sub_ptr,
+                                  const int32_t* sub_idx, const int32_t* inc_size, const uint8_t* keep, int n_inc,
+                                  int order, const double* misc_in, double* eps, double* out, int32_t* bad,
+                                  hipStream_t st);
+hipError_t launch_mark_screened(const uint8_t* keep, int64_t first, int64_t count, double* e_out,
+                                int32_t* status_out, int32_t* iters_out, double* resid_out, hipStream_t st);
 hipError_t launch_energy(const double* e_inc, const int32_t* status, const int32_t* sub_ptr,
                          const int32_t* sub_idx, const int32_t* inc_size, int n_inc, int order,
                          const double* misc_in, double* eps, double* out, int32_t* bad,
                          hipStream_t st);
 
 hipError_t launch_rdm(const IncDev* incs, const IncDev* host_incs, int n_inc, const double* dav_base,
-                      const int32_t* tables, double* rdm, const int64_t* rdm_off_dev, int mmax,
+                      const int32_t* tables, double* rdm, const int64_t* rdm_off_dev, int mmax, const uint8_t* keep,
                       hipStream_t st);
 hipError_t launch_rdm_accumulate(const IncDev* incs, int n_inc, const int32_t* orbs,
                                  const int32_t* loc, const double* rdm, const int64_t* rdm_off_dev,

@@ -75,6 +75,10 @@ struct ifci_plan_s {
   bool on_device = false;
   int64_t* phase_counters = nullptr;  // tracing: per-increment phase clocks
   std::vector<int32_t> h_sub_ptr, h_sub_idx, h_inc_size;
+  // connected n-body screening (ifci_screen): mask (empty: none) and its
+  // device copy
+  std::vector<uint8_t> keep;
+  uint8_t* d_keep = nullptr;
   std::vector<int8_t> h_loc;
   std::vector<double> h_w_inc;
   int64_t ref_off = 0;               // reference-occupied orbitals in the orbital blob

@@ -32,8 +32,10 @@ __global__ void __launch_bounds__(kRdmThreads) rdm_kernel(const IncDev* __restri
                                                           const double* __restrict__ dav,
                                                           const int32_t* __restrict__ tables,
                                                           double* __restrict__ rdm,
-                                                          const int64_t* __restrict__ rdm_off, int mmax) {
+                                                          const int64_t* __restrict__ rdm_off, int mmax,
+                                                          const uint8_t* __restrict__ keep) {
   extern __shared__ __align__(16) char lds[];
+  if (keep && !keep[blockIdx.x]) return;  // dropped by the screening: no vector
   const IncDev d = incs[blockIdx.x];
   const int k = d.k, k2 = k * k, n = d.n_str;
   const int nt = (k2 + 15) / 16;          // tiles per side
@@ -133,7 +135,8 @@ __global__ void __launch_bounds__(kRdmThreads) rdm_kernel(const IncDev* __restri
 
 // Gamma_pqrs -= delta_qr gamma_ps, one thread per (p, q, s)
 __global__ void rdm_delta_kernel(const IncDev* __restrict__ incs, double* __restrict__ rdm,
-                                 const int64_t* __restrict__ rdm_off) {
+                                 const int64_t* __restrict__ rdm_off, const uint8_t* __restrict__ keep) {
+  if (keep && !keep[blockIdx.x]) return;
   const IncDev d = incs[blockIdx.x];
   const int k = d.k, k2 = k * k;
   double* out = rdm + rdm_off[blockIdx.x];
@@ -144,7 +147,7 @@ __global__ void rdm_delta_kernel(const IncDev* __restrict__ incs, double* __rest
 }
 
 hipError_t launch_rdm(const IncDev* incs, const IncDev* host_incs, int n_inc, const double* dav_base,
-                      const int32_t* tables, double* rdm, const int64_t* rdm_off_dev, int mmax,
+                      const int32_t* tables, double* rdm, const int64_t* rdm_off_dev, int mmax, const uint8_t* keep,
                       hipStream_t st) {
   const hipError_t e = allow_max_lds((const void*)rdm_kernel);
   if (e != hipSuccess) return e;
@@ -155,8 +158,8 @@ hipError_t launch_rdm(const IncDev* incs, const IncDev* host_incs, int n_inc, co
   const size_t lds = (size_t)(nt * 16) * kRdmChunk * 8 + kRdmChunk * 8 + (size_t)kmax * kmax * 8 + 64;
   if (lds > (size_t)kMaxLds) return hipErrorInvalidValue;
   hipLaunchKernelGGL(rdm_kernel, dim3(n_inc, groups), dim3(kRdmThreads), lds, st, incs, dav_base, tables, rdm,
-                     rdm_off_dev, mmax);
-  hipLaunchKernelGGL(rdm_delta_kernel, dim3(n_inc), dim3(256), 0, st, incs, rdm, rdm_off_dev);
+                     rdm_off_dev, mmax, keep);
+  hipLaunchKernelGGL(rdm_delta_kernel, dim3(n_inc), dim3(256), 0, st, incs, rdm, rdm_off_dev, keep);
   return hipGetLastError();
 }
 

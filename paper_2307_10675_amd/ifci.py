@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libifci.so")
 
 FP64, MIXED = 0, 1
 BATCHED, PLAIN = 0, 1
-INC_PENDING, INC_DONE, INC_NOT_CONVERGED, INC_EVICTED = 0, 1, 2, 3
+INC_PENDING, INC_DONE, INC_NOT_CONVERGED, INC_EVICTED, INC_SCREENED = 0, 1, 2, 3, 4
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "out of memory", 4: "device error",
           5: "not converged", 6: "invalid state"}
 
@@ -75,6 +75,8 @@ _SIGNATURES = {
     "ifci_rdm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.c_void_p]),
     "ifci_set_phase_counters": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
+    "ifci_screen": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                                   ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
     "ifci_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32]),
     "ifci_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -279,6 +281,16 @@ class Plan:
                                    _stream(stream)))
         return e, st, it, rs
 
+    def screen(self, e_inc, threshold: float, stream=None):
+        """Connected n-body screening (ifci_screen) from the one- and
+        two-body energies in e_inc (device [n_inc]); threshold < 0 removes it.
+        Returns the keep mask (numpy bool [n_inc])."""
+        keep = np.zeros(self.n_inc, dtype=np.uint8)
+        n = ctypes.c_int64()
+        _check(lib().ifci_screen(self._h, _ptr(e_inc), float(threshold), keep.ctypes.data_as(ctypes.c_void_p),
+                                 ctypes.byref(n), _stream(stream)))
+        return keep.astype(bool)
+
     def set_tuning(self, k: int, precision: int, ps_block: int = -1, e_waves: int = 0):
         """Per-shape settings of the on-chip solvers (ifci_set_tuning)."""
         _check(lib().ifci_set_tuning(self._h, int(k), int(precision), int(ps_block), int(e_waves)))
@@ -342,6 +354,30 @@ def davidson_group(plans, stream=None):
     _check(lib().ifci_davidson_group(handles, len(plans), arr([o[0] for o in outs]), arr([o[1] for o in outs]),
                                      arr([o[2] for o in outs]), arr([o[3] for o in outs]), _stream(stream)))
     return outs
+
+
+def solve_screened(problem, threshold: float, precision=FP64, solver=BATCHED, device: int = 0, **opts):
+    """The expansion with connected n-body screening: the one- and two-body
+    increments first, then ifci_screen on their energies, then the kept
+    increments of three or more bodies, and the screened energy sums."""
+    import torch
+    plan = Plan(problem, precision=precision, solver=solver, device=device, **opts)
+    plan.attach(problem.h, problem.eri)
+    sizes = [len(i.bodies) for i in plan.increments()]
+    n12 = sum(1 for s in sizes if s <= 2)
+    dev = torch.device("cuda", device)
+    e = torch.full((plan.n_inc,), float("nan"), dtype=torch.float64, device=dev)
+    st = torch.zeros(plan.n_inc, dtype=torch.int32, device=dev)
+    it = torch.zeros(plan.n_inc, dtype=torch.int32, device=dev)
+    rs = torch.zeros(plan.n_inc, dtype=torch.float64, device=dev)
+    e1, s1, i1, r1 = plan.davidson(0, n12)
+    e[:n12], st[:n12], it[:n12], rs[:n12] = e1, s1, i1, r1
+    keep = plan.screen(e, threshold)
+    if plan.n_inc > n12:
+        e2, s2, i2, r2 = plan.davidson(n12, plan.n_inc - n12)
+        e[n12:], st[n12:], it[n12:], rs[n12:] = e2, s2, i2, r2
+    en = plan.energy(e, st)
+    return plan, dict(E=e, status=st, iters=it, resid=rs, keep=keep, **en)
 
 
 def solve(problem, precision=FP64, solver=BATCHED, device: int = 0, **opts):

@@ -70,10 +70,11 @@ def _sym_upper(rng, n, scale, include_diag):
     return a + np.triu(a, 1).T
 
 
-def integrals(n_orb: int, n_chol: int, seed: int, body_of=None, decay: bool = False):
+def integrals(n_orb: int, n_chol: int, seed: int, body_of=None, decay: bool = False, rate: float = 0.5):
     """Draw (h, eri) as described in the module docstring.
 
-    body_of: array of body labels per orbital (used only for the decay)."""
+    body_of: array of body labels per orbital (used only for the decay);
+    rate: the decay factor is exp(-rate |body distance|)."""
     rng = np.random.default_rng(seed)
     diag = rng.uniform(-1.5, 0.5, size=n_orb)
     off = _sym_upper(rng, n_orb, 0.05, include_diag=False)
@@ -82,7 +83,7 @@ def integrals(n_orb: int, n_chol: int, seed: int, body_of=None, decay: bool = Fa
     L = np.stack([_sym_upper(rng, n_orb, 0.15, include_diag=True) for _ in range(n_chol)])
     if decay:
         b = np.asarray(body_of)
-        d = np.exp(-0.5 * np.abs(b[:, None] - b[None, :]))
+        d = np.exp(-rate * np.abs(b[:, None] - b[None, :]))
         h = h * np.where(np.eye(n_orb, dtype=bool), 1.0, d)
         L = L * d[None]
     eri = np.einsum("kpq,krs->pqrs", L, L)
@@ -98,16 +99,19 @@ def _order_body(h, orbs, nocc):
 
 
 def chain(n_bodies: int, orbs_per_body: int = 2, nocc_per_body: int = 1, n_chol: int = 12,
-          seed: int = 0, order: int = 1, decay: bool = True) -> Problem:
-    """A 1-D chain of equal bodies {b*m, ..., b*m + m - 1}."""
+          seed: int = 0, order: int = 1, decay: bool = True, rate: float = 0.5) -> Problem:
+    """A 1-D chain of equal bodies {b*m, ..., b*m + m - 1}; with decay the
+    couplings between bodies fall off as exp(-rate |body distance|)."""
     n_orb = n_bodies * orbs_per_body
     body_of = np.arange(n_orb) // orbs_per_body
-    h, eri = integrals(n_orb, n_chol, seed, body_of=body_of, decay=decay)
+    h, eri = integrals(n_orb, n_chol, seed, body_of=body_of, decay=decay, rate=rate)
     bodies = [_order_body(h, list(range(b * orbs_per_body, (b + 1) * orbs_per_body)), nocc_per_body)
               for b in range(n_bodies)]
-    return Problem(h, eri, bodies, [nocc_per_body] * n_bodies, order,
-                   meta=dict(kind="chain", n_bodies=n_bodies, orbs_per_body=orbs_per_body,
-                             n_chol=n_chol, seed=seed, decay=decay))
+    meta = dict(kind="chain", n_bodies=n_bodies, orbs_per_body=orbs_per_body, n_chol=n_chol, seed=seed,
+                decay=decay)
+    if rate != 0.5:
+        meta["rate"] = rate
+    return Problem(h, eri, bodies, [nocc_per_body] * n_bodies, order, meta=meta)
 
 
 def single(n_orb: int, n_chol: int, seed: int) -> Problem:
@@ -140,6 +144,36 @@ def separable(n_bodies: int, n_chol: int = 12, seed: int = 0, order: int = 2) ->
     bodies = [[2 * b, 2 * b + 1] for b in range(n_bodies)]
     return Problem(h, eri, bodies, [1] * n_bodies, order,
                    meta=dict(kind="separable", n_bodies=n_bodies, n_chol=n_chol, seed=seed))
+
+
+def local_chain(n_bodies: int, seed: int = 0, order: int = 1, rate: float = 1.0, coupling: float = 0.3,
+                n_chol: int = 4) -> Problem:
+    """Chain of 2-orbital bodies whose every interaction falls off with the
+    distance along the chain, also the integrals (ia|jb) that correlate two
+    bodies (in the chain above they do not decay).  Each body is drawn as
+    in `separable`; on top, every body centre c carries n_chol shared factors
+    M[p][q] = coupling * g_pq * exp(-rate (|b(p) - c| + |b(q) - c|)), g
+    symmetric N(0, 0.15), added to the eri as sum M (x) M (so it stays
+    8-fold symmetric and positive semidefinite), and h couples bodies I, J by
+    N(0, 0.05) * exp(-rate |I - J|)."""
+    p = separable(n_bodies, seed=seed, order=order)
+    n_orb = 2 * n_bodies
+    rng = np.random.default_rng(seed + 7919)
+    b = np.arange(n_orb) // 2
+    h = p.h.copy()
+    off = _sym_upper(rng, n_orb, 0.05, include_diag=False)
+    dist = np.abs(b[:, None] - b[None, :])
+    h = h + np.where(dist > 0, off * np.exp(-rate * dist), 0.0)
+    eri = p.eri.copy()
+    for c in range(n_bodies):
+        f = np.exp(-rate * np.abs(b - c))
+        for _ in range(n_chol):
+            M = coupling * _sym_upper(rng, n_orb, 0.15, include_diag=True) * f[:, None] * f[None, :]
+            eri += np.einsum("pq,rs->pqrs", M, M)
+    bodies = [_order_body(h, [2 * i, 2 * i + 1], 1) for i in range(n_bodies)]
+    return Problem(h, eri, bodies, [1] * n_bodies, order,
+                   meta=dict(kind="local_chain", n_bodies=n_bodies, seed=seed, rate=rate, coupling=coupling,
+                             n_chol=n_chol))
 
 
 def random_vector(n: int, seed: int, symmetric_dim: int | None = None) -> np.ndarray:

@@ -136,6 +136,10 @@ def main():
     todo["wide_9o6e"] = (p9, ifci.increments(3, 3), True)
     p12 = synthetic.chain(2, orbs_per_body=6, nocc_per_body=1, seed=3124, order=2)
     todo["wide_12o4e"] = (p12, ifci.increments(2, 2), True)
+    # a chain whose pair increments fall off with distance (for the
+    # connected n-body screening)
+    pl = synthetic.local_chain(10, seed=5100, order=4, rate=1.0)
+    todo["local10"] = (pl, ifci.increments(pl.n_bodies, pl.order), True)
     for name, (p, subsets, full) in todo.items():
         if a.only and a.only != name:
             continue

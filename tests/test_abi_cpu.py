@@ -160,3 +160,16 @@ def test_set_tuning_arguments(L, tmp_path):
     b = ifci.Plan(p, tuning=t)
     b.close()
     a.close()
+
+
+def test_screen_needs_solved_plan(L):
+    """ifci_screen refuses a plan without workspace and integrals (no device
+    work), and an invalid plan."""
+    import ctypes
+    from paper_2307_10675_amd import ifci, synthetic
+    p = synthetic.chain(3, seed=1, order=3)
+    a = ifci.Plan(p, tuning=None)
+    n = ctypes.c_int64()
+    assert L.ifci_screen(a._h, ctypes.c_void_p(256), 1e-4, None, ctypes.byref(n), None) == 6
+    assert L.ifci_screen(None, ctypes.c_void_p(256), 1e-4, None, ctypes.byref(n), None) == 1
+    a.close()

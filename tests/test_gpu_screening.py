@@ -1,0 +1,99 @@
+"""GPU parity of connected n-body screening (ifci_screen; the CnB paragraph
+of the paper's iFCI section, with the reading stated in oracle/screening.py)
+on a chain whose pair increments fall off with distance: the kept set, the
+dropped increments' status, the kept increments' energies, eps and the
+screened total against the oracle's screened sums of its exact increment
+energies (tests/golden/oracle_local10.json), and the gradient of the
+screened expansion against the oracle's densities weighted by the screened
+coefficients."""
+import numpy as np
+import pytest
+
+from oracle import fci, ifci as oifci, rdm as ordm, screening
+from paper_2307_10675_amd import ifci, synthetic
+from tests.helpers import load_golden
+
+pytestmark = pytest.mark.gpu
+
+C = 10 ** -4.6  # the paper's screening parameter (Eh)
+
+
+@pytest.mark.parametrize("precision,r_tol,tol", [(ifci.FP64, 1e-8, 1e-9), (ifci.MIXED, 1e-5, 1e-6)])
+def test_screened_expansion_against_oracle(precision, r_tol, tol):
+    p = synthetic.local_chain(10, seed=5100, order=4, rate=1.0)
+    g = load_golden("local10")
+    assert p.sha256() == g["sha256"], "synthetic generator changed; regenerate tests/golden"
+    E = {tuple(x["bodies"]): x["E"] for x in g["increments"]}
+    e_ref = g["e_ref"]
+    eps2 = screening.pair_increments(E, e_ref, 10)
+    # every pair decision is far from the threshold compared with the error
+    # the solver may leave in a pair increment
+    assert min(abs(abs(v) - C) for v in eps2.values()) > 100 * tol
+    keep_o = screening.cnb_keep(E, e_ref, 10, 4, C)
+    eps_o, by_o, tot_o = screening.screened_expansion(E, e_ref, 4, keep_o)
+    sizes = [len(S) for S in keep_o]
+    assert sizes.count(3) < 120 and sizes.count(4) < 210, "nothing dropped: the test would not test screening"
+    print(f"[cnb] kept {sizes.count(3)} of 120 three-body and {sizes.count(4)} of 210 four-body", flush=True)
+    plan, res = ifci.solve_screened(p, C, precision=precision, r_tol=r_tol, r_tol_inner=1e-5, max_iter=500)
+    incs = [i.bodies for i in plan.increments()]
+    assert [S for S, k in zip(incs, res["keep"]) if k] == keep_o
+    st = res["status"].cpu().numpy()
+    e = res["E"].cpu().numpy()
+    eps = res["eps"].cpu().numpy()
+    for i, S in enumerate(incs):
+        if res["keep"][i]:
+            assert st[i] == ifci.INC_DONE
+            assert abs(e[i] - E[S]) <= tol, S
+            assert abs(eps[i] - eps_o[S]) <= tol * 2 ** len(S), S
+        else:
+            assert st[i] == ifci.INC_SCREENED and np.isnan(e[i]) and eps[i] == 0.0
+    assert res["converged"]
+    tol_sum = 1e-8 if precision == ifci.FP64 else 1e-5
+    assert abs(res["total"] - tot_o) <= tol_sum
+    assert np.abs(np.array(res["by_order"]) - np.array(by_o)).max() <= tol_sum
+
+
+def test_threshold_zero_and_removed_mask_equal_the_full_expansion():
+    import torch
+    p = synthetic.local_chain(6, seed=5102, order=3, rate=1.0)
+    _, full = ifci.solve(p, r_tol=1e-9, max_iter=500)
+    plan, zero = ifci.solve_screened(p, 0.0, r_tol=1e-9, max_iter=500)
+    assert all(zero["keep"])
+    assert abs(zero["total"] - full["total"]) <= 1e-10
+    # a negative threshold removes the mask: the closed-form sums again
+    keep = plan.screen(zero["E"], -1.0)
+    assert keep.all()
+    again = plan.energy(zero["E"], zero["status"])
+    torch.cuda.synchronize()
+    assert abs(again["total"] - full["total"]) <= 1e-10
+
+
+def test_screened_gradient_against_oracle():
+    """dE/dh and dE/d(pq|rs) of the screened expansion: each kept
+    increment's densities weighted by its coefficient in the screened sum,
+    the reference's by one minus their sum."""
+    import torch
+    p = synthetic.local_chain(5, seed=5101, order=3, rate=1.0)
+    E = {S: fci.solve_increment(p, S)["E"] for S in oifci.increments(5, 2)}
+    e_ref = oifci.reference_energy(p)
+    eps2 = screening.pair_increments(E, e_ref, 5)
+    thr = 1e-4
+    assert min(abs(abs(v) - thr) for v in eps2.values()) > 1e-7
+    keep_o = screening.cnb_keep(E, e_ref, 5, 3, thr)
+    assert len(keep_o) < len(oifci.increments(5, 3)), "nothing dropped"
+    coef = screening.screened_coefficients(keep_o, 3)
+    g_ref, G_ref = ordm.reference_densities(p)
+    dh_o = (1.0 - sum(coef.values())) * g_ref
+    dg_o = 0.5 * (1.0 - sum(coef.values())) * G_ref
+    for S, c in coef.items():
+        d = ordm.increment_densities(p, S)
+        dh_o = dh_o + c * d["gamma"]
+        dg_o = dg_o + 0.5 * c * d["Gamma"]
+    plan, res = ifci.solve_screened(p, thr, r_tol=1e-10, max_iter=500)
+    dh, dg = plan.rdm()
+    torch.cuda.synchronize()
+    dh, dg = dh.cpu().numpy(), dg.cpu().numpy()
+    assert np.abs(dh - dh_o).max() <= 1e-8
+    assert np.abs(dg - dg_o).max() <= 1e-8
+    e_euler = float((p.h * dh).sum() + (p.eri * dg).sum())
+    assert abs(e_euler - res["total"]) <= 1e-9
