@@ -280,6 +280,22 @@ ifci_status ifci_davidson_group(const ifci_plan_t* plans, int32_t n_plans, doubl
 ifci_status ifci_screen(ifci_plan_t plan, const double* e_inc, double threshold, uint8_t* keep,
                         int64_t* n_kept, ifci_stream_t stream);
 
+/* Grouped contributions (paper, Results, the PFAS bond-breaking analysis and
+ * its Fig. 4): each body carries a group label (group_of_body, host
+ * [n_bodies], values 0 .. n_groups - 1), and every increment belongs to the
+ * combination of its bodies' labels, a multiset written as the sorted label
+ * list.  ifci_group_count gives the number of combinations of 1 .. order
+ * labels; ifci_group_sums fills sums (host [n_combos]) with the sum of eps_S
+ * (device [n_inc], from ifci_energy) over each combination's increments, in
+ * increment order with compensated addition, and combos (host
+ * [n_combos][order], may be NULL) with the labels, -1 padded; combinations
+ * run by size, then lexicographically.  The difference of two calculations
+ * with comparable orbitals (two geometries) is the difference of their
+ * sums.  Synchronises the stream.  IFCI_ERR_ARG for a label out of range. */
+ifci_status ifci_group_count(ifci_plan_t plan, int32_t n_groups, int64_t* n_combos);
+ifci_status ifci_group_sums(ifci_plan_t plan, const double* eps, const int32_t* group_of_body, int32_t n_groups,
+                            double* sums, int32_t* combos, ifci_stream_t stream);
+
 /* Copy the converged unit vector of increment inc (device [n_det]). */
 ifci_status ifci_vector(ifci_plan_t plan, int64_t inc, double* c_out, ifci_stream_t stream);
 

@@ -1024,6 +1024,83 @@ ifci_status ifci_screen(ifci_plan_t p, const double* e_inc, double threshold, ui
   return IFCI_OK;
 }
 
+namespace {
+// Every non-decreasing label sequence of length 1 .. order over n_groups
+// labels, by length, then lexicographically.
+std::vector<std::vector<int>> label_combinations(int n_groups, int order) {
+  std::vector<std::vector<int>> out;
+  for (int k = 1; k <= order; ++k) {
+    std::vector<int> c(k, 0);
+    while (true) {
+      out.push_back(c);
+      int j = k - 1;
+      while (j >= 0 && c[j] == n_groups - 1) --j;
+      if (j < 0) break;
+      ++c[j];
+      for (int l = j + 1; l < k; ++l) c[l] = c[j];
+    }
+  }
+  return out;
+}
+}  // namespace
+
+ifci_status ifci_group_count(ifci_plan_t p, int32_t n_groups, int64_t* n_combos) {
+  if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
+  if (n_groups < 1 || n_groups > 64 || !n_combos) {
+    set_error("ifci_group_count: n_groups 1..64 and an output");
+    return IFCI_ERR_ARG;
+  }
+  // multisets of k labels from n_groups: C(n_groups + k - 1, k)
+  int64_t n = 0;
+  for (int k = 1; k <= p->order; ++k) {
+    double c = 1.0;
+    for (int j = 1; j <= k; ++j) c = c * (n_groups + k - j) / j;
+    n += (int64_t)(c + 0.5);
+  }
+  *n_combos = n;
+  return IFCI_OK;
+}
+
+ifci_status ifci_group_sums(ifci_plan_t p, const double* eps, const int32_t* group_of_body, int32_t n_groups,
+                            double* sums, int32_t* combos, ifci_stream_t stream) {
+  if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
+  if (!eps || !group_of_body || !sums || n_groups < 1 || n_groups > 64) {
+    set_error("ifci_group_sums: null pointer or n_groups outside 1..64");
+    return IFCI_ERR_ARG;
+  }
+  for (int b = 0; b < p->n_bodies; ++b)
+    if (group_of_body[b] < 0 || group_of_body[b] >= n_groups) {
+      set_error("ifci_group_sums: label of body " + std::to_string(b) + " out of range");
+      return IFCI_ERR_ARG;
+    }
+  const int n_inc = (int)p->inc.size();
+  DeviceGuard g(p->device);
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<double> e(n_inc);
+  HIP_TRY(hipMemcpyAsync(e.data(), eps, sizeof(double) * n_inc, hipMemcpyDeviceToHost, st), "ifci_group_sums");
+  HIP_TRY(hipStreamSynchronize(st), "ifci_group_sums");
+  const std::vector<std::vector<int>> all = label_combinations(n_groups, p->order);
+  std::map<std::vector<int>, size_t> index;
+  for (size_t c = 0; c < all.size(); ++c) index[all[c]] = c;
+  std::vector<double> s(all.size(), 0.0), comp(all.size(), 0.0);
+  for (int i = 0; i < n_inc; ++i) {
+    std::vector<int> lab;
+    for (int b : p->inc_bodies[i]) lab.push_back(group_of_body[b]);
+    std::sort(lab.begin(), lab.end());
+    const size_t c = index.at(lab);
+    // Neumaier-compensated running sum
+    const double x = e[i], t = s[c] + x;
+    comp[c] += std::fabs(s[c]) >= std::fabs(x) ? (s[c] - t) + x : (x - t) + s[c];
+    s[c] = t;
+  }
+  for (size_t c = 0; c < all.size(); ++c) {
+    sums[c] = s[c] + comp[c];
+    if (combos)
+      for (int j = 0; j < p->order; ++j) combos[c * p->order + j] = j < (int)all[c].size() ? all[c][j] : -1;
+  }
+  return IFCI_OK;
+}
+
 ifci_status ifci_vector(ifci_plan_t p, int64_t inc, double* c_out, ifci_stream_t stream) {
   if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
   if (inc < 0 || inc >= (int64_t)p->inc.size() || !c_out) {

@@ -77,6 +77,9 @@ _SIGNATURES = {
     "ifci_set_phase_counters": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
     "ifci_screen": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
                                    ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
+    "ifci_group_count": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "ifci_group_sums": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "ifci_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32]),
     "ifci_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -88,6 +91,11 @@ def lib():
     """The loaded libifci.  Raises if the library has not been built."""
     global _lib
     if _lib is None:
+        # torch first: it carries its own HIP runtime, and the library must
+        # bind to that one (loaded first, the library would bring up a second
+        # runtime beside torch's, which then sees no device for torch's
+        # memory: hipSetDevice fails with an invalid ordinal)
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"libifci.so not found at {LIB_PATH}; build it with "
                                "`python -m paper_2307_10675_amd.build`")
@@ -291,6 +299,19 @@ class Plan:
                                  ctypes.byref(n), _stream(stream)))
         return keep.astype(bool)
 
+    def group_sums(self, eps, group_of_body, n_groups: int | None = None, stream=None):
+        """{combination (sorted label tuple): sum of eps_S} (ifci_group_sums)."""
+        lab = np.ascontiguousarray(group_of_body, dtype=np.int32)
+        ng = int(n_groups if n_groups is not None else lab.max() + 1)
+        n = ctypes.c_int64()
+        _check(lib().ifci_group_count(self._h, ng, ctypes.byref(n)))
+        sums = np.zeros(n.value)
+        combos = np.zeros((n.value, self.order), dtype=np.int32)
+        _check(lib().ifci_group_sums(self._h, _ptr(eps), lab.ctypes.data_as(ctypes.c_void_p), ng,
+                                     sums.ctypes.data_as(ctypes.c_void_p), combos.ctypes.data_as(ctypes.c_void_p),
+                                     _stream(stream)))
+        return {tuple(int(x) for x in c if x >= 0): float(v) for c, v in zip(combos, sums)}
+
     def set_tuning(self, k: int, precision: int, ps_block: int = -1, e_waves: int = 0):
         """Per-shape settings of the on-chip solvers (ifci_set_tuning)."""
         _check(lib().ifci_set_tuning(self._h, int(k), int(precision), int(ps_block), int(e_waves)))
@@ -354,6 +375,13 @@ def davidson_group(plans, stream=None):
     _check(lib().ifci_davidson_group(handles, len(plans), arr([o[0] for o in outs]), arr([o[1] for o in outs]),
                                      arr([o[2] for o in outs]), arr([o[3] for o in outs]), _stream(stream)))
     return outs
+
+
+def group_differences(sums_a: dict, sums_b: dict):
+    """Per combination the change from calculation a to calculation b (two
+    geometries with comparable orbitals): sums_b - sums_a."""
+    return {c: sums_b.get(c, 0.0) - sums_a.get(c, 0.0) for c in sorted(set(sums_a) | set(sums_b),
+                                                                      key=lambda c: (len(c), c))}
 
 
 def solve_screened(problem, threshold: float, precision=FP64, solver=BATCHED, device: int = 0, **opts):
