@@ -41,7 +41,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp64_mfma": 78.6e12, "fp32_mfma": 157.3e12, "hbm": 8.0e12}
-KERNEL_SOURCES = ["batched.hip", "device_common.hpp", "ifci_internal.h", "launch.hpp"]
+KERNEL_SOURCES = ["batched.hip", "pspace.hpp", "device_common.hpp", "ifci_internal.h", "launch.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batched_lobpcg_kernel_workload2.traffic.json")
 ORACLE_W2 = os.path.join(ROOT, "tests", "golden", "oracle_w2.json")
 ALL_LEGS = ("mixed", "fp64", "plain", "large", "w3", "w4", "cpu")
@@ -364,6 +364,8 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 14o14e and 16o16e measurements")
     ap.add_argument("--cpu-workers", type=int, default=0, help="oracle pool size (default: min(16, cores))")
     ap.add_argument("--cpu-8o8e", type=int, default=CPU_8O8E_SAMPLE)
+    ap.add_argument("--no-untuned", action="store_true",
+                    help="skip the leg with the built-in settings beside the tuned ones (profile runs)")
     ap.add_argument("--max-space", type=int, default=SPACE,
                     help="batched solver subspace (3: three-vector iteration, 4..16: thick-restart Davidson)")
     ap.add_argument("--n-guess", type=int, default=None,
@@ -461,7 +463,7 @@ def main():
     # the tuner's per-shape settings (tuning.json, applied by Plan) against
     # the built-in choices
     tuning = ifci.load_tuning()
-    if tuning and "mixed" in legs:
+    if tuning and "mixed" in legs and not a.no_untuned:
         untuned = measure(ifci.MIXED, ifci.BATCHED, max(1, a.steps // 2), 1, max_space=a.max_space,
                           n_guess=n_guess, tuning=None)
         out_detail["tuning"] = {
