@@ -226,20 +226,27 @@ ifci_status ifci_sigma_sector(ifci_plan_t plan, int64_t inc, const double* c, do
 
 /* Lowest even-spin root of increments [first, first + count): E(S) of every
  * increment S of eqs. 1-5 (Methods, iFCI), by Davidson's method (J. Comput.
- * Phys. 17, 87, 1975) with a diagonal preconditioner, thick restart or the
- * three-vector {x, w, p} form (locally optimal, Knyazev) per max_space.
+ * Phys. 17, 87, 1975), thick restart or the three-vector {x, w, p} form
+ * (locally optimal, Knyazev) per max_space; on chip started from and
+ * preconditioned by the P-space block of n_guess, device-wide from the
+ * lowest determinant with the diagonal preconditioner.
  * e_out: device [count] total energies E(S) (frozen core and e_const
  * included); status_out: device [count] IFCI_INC_* words; evict_mask: device
  * [count] or NULL -- increments whose byte is nonzero are abandoned after one
  * iteration and reported EVICTED (failure injection); iters_out/resid_out:
  * device [count] or NULL.  Converged vectors stay in the workspace for
- * ifci_vector and ifci_rdm.  Increments that fit on chip run in one launch of
- * the batched solver; the others (more than 8 active orbitals, or the plain
- * solver) run device-wide, up to 8 at a time on streams the plan owns, each
- * driven by a host thread: that work starts after what is already queued on
- * `stream` and `stream` continues after it, so the call keeps stream order.
- * The call returns when the device-wide solves have been issued (each waits
- * on the host once per iteration). */
+ * ifci_vector and ifci_rdm.  Increments dropped by a screening mask
+ * (ifci_screen) are not solved: status IFCI_INC_SCREENED, energy NaN.
+ * Increments that fit on chip run in one launch of the batched solver; the
+ * others (more than 8 active orbitals) run in the batched device-wide
+ * solver, every increment of a shape in the same launches, its iterations
+ * replayed from a captured graph with restart, precision switch and stop
+ * decided on the device (with IFCI_FLAG_ASYNC_WIDE the host never reads the
+ * live count and the call only enqueues).  With the plain solver every
+ * increment runs device-wide on its own, up to 8 at a time on streams the
+ * plan owns, each driven by a host thread; that work starts after what is
+ * already queued on `stream` and `stream` continues after it, so the call
+ * keeps stream order. */
 ifci_status ifci_davidson(ifci_plan_t plan, int64_t first, int64_t count, double* e_out,
                           int32_t* status_out, const uint8_t* evict_mask, int32_t* iters_out,
                           double* resid_out, ifci_stream_t stream);
@@ -318,7 +325,8 @@ ifci_status ifci_energy(ifci_plan_t plan, const double* e_inc, const int32_t* st
  * of H: the 1- and 2-particle density matrices of the converged vector),
  * weighted as the expansion of eqs. 1-5 weights each E(S): dE_dh (device [n*n]) = weighted 1-RDM gamma,
  * dE_deri (device [n^4], may be NULL) = weighted Gamma / 2.  Needs the
- * converged vectors of every increment (ifci_davidson first). */
+ * converged vectors of every increment that is not screened out
+ * (ifci_davidson first). */
 ifci_status ifci_rdm(ifci_plan_t plan, const double* weights, double* dE_dh, double* dE_deri,
                      ifci_stream_t stream);
 
