@@ -303,6 +303,41 @@ ifci_status ifci_group_count(ifci_plan_t plan, int32_t n_groups, int64_t* n_comb
 ifci_status ifci_group_sums(ifci_plan_t plan, const double* eps, const int32_t* group_of_body, int32_t n_groups,
                             double* sums, int32_t* combos, ifci_stream_t stream);
 
+/* Summation natural orbitals (paper, Methods, iFCI subsection, the SNO
+ * paragraph, eq. 6) for a system whose bodies are single occupied orbitals
+ * sharing the virtual orbitals vir (device [n_vir], n_vir <= 16).  gamma:
+ * device [n_occ][n_orb][n_orb], per occupied orbital the one-particle
+ * density of the FCI of its two electrons in itself plus every virtual,
+ * the other occupied orbitals frozen (exact CISD for two electrons: solve it
+ * as a one-body problem and take ifci_rdm with weight 1 on that increment).
+ * inc_occ: device [n_inc][order], the occupied-orbital positions (0 ..
+ * n_occ - 1) of each increment, -1 padded.  For each increment rho_S = sum
+ * of its members' blocks over vir; its natural orbitals (eigenvectors, one
+ * wavefront each, parallel Jacobi) with occupation >= 10^-eta are written as
+ * the first n_keep[inc] columns of rot (device [n_inc][n_vir][n_vir], row =
+ * virtual, largest occupation first, the other columns zero); n_keep:
+ * device [n_inc].  Stream-ordered; allocates nothing. */
+ifci_status ifci_sno_orbitals(const double* gamma, int32_t n_orb, const int32_t* vir, int32_t n_vir,
+                              const int32_t* inc_occ, int64_t n_inc, int32_t order, double eta, double* rot,
+                              int32_t* n_keep, ifci_stream_t stream);
+
+/* The integrals of one SNO increment in its rotated basis: m = n_s + n_keep
+ * + n_other orbitals, in order S's occupied orbitals, the first n_keep
+ * columns of rot (that increment's [n_vir][n_vir] block from
+ * ifci_sno_orbitals) over vir, the other occupied orbitals; col_orb (device
+ * [n_s + n_other]) the full-space indices of the occupied ones in that
+ * order.  h_out = C^T h C (device [m][m]) and eri_out (device [m^4], chemist
+ * order) by four quarter transformations of eri (device [n_orb^4]); work:
+ * device [work_doubles], at least n_orb m + 2 n_orb^3 m (IFCI_ERR_ARG
+ * otherwise, before any device work).  The increment is then an
+ * ordinary problem over these integrals: one body of its first n_s + n_keep
+ * orbitals with n_s occupied, and one frozen body per other occupied
+ * orbital.  Stream-ordered; allocates nothing. */
+ifci_status ifci_sno_transform(const double* h, const double* eri, int32_t n_orb, const int32_t* vir, int32_t n_vir,
+                               const int32_t* col_orb, int32_t n_s, int32_t n_other, const double* rot,
+                               int32_t n_keep, double* work, int64_t work_doubles, double* h_out, double* eri_out,
+                               ifci_stream_t stream);
+
 /* Copy the converged unit vector of increment inc (device [n_det]). */
 ifci_status ifci_vector(ifci_plan_t plan, int64_t inc, double* c_out, ifci_stream_t stream);
 

@@ -1101,6 +1101,46 @@ ifci_status ifci_group_sums(ifci_plan_t p, const double* eps, const int32_t* gro
   return IFCI_OK;
 }
 
+ifci_status ifci_sno_orbitals(const double* gamma, int32_t n_orb, const int32_t* vir, int32_t n_vir,
+                              const int32_t* inc_occ, int64_t n_inc, int32_t order, double eta, double* rot,
+                              int32_t* n_keep, ifci_stream_t stream) {
+  if (!gamma || !vir || !inc_occ || !rot || !n_keep || n_orb < 1 || n_orb > 64 || n_vir < 1 || n_vir > 16 ||
+      n_inc < 1 || order < 1 || std::isnan(eta)) {
+    set_error("ifci_sno_orbitals: null pointer, n_orb 1..64, n_vir 1..16, n_inc >= 1, order >= 1");
+    return IFCI_ERR_ARG;
+  }
+  HIP_TRY(launch_sno_orbitals(gamma, n_orb, vir, n_vir, inc_occ, n_inc, order, std::pow(10.0, -eta), rot, n_keep,
+                              (hipStream_t)stream),
+          "ifci_sno_orbitals");
+  return IFCI_OK;
+}
+
+ifci_status ifci_sno_transform(const double* h, const double* eri, int32_t n_orb, const int32_t* vir, int32_t n_vir,
+                               const int32_t* col_orb, int32_t n_s, int32_t n_other, const double* rot,
+                               int32_t n_keep, double* work, int64_t work_doubles, double* h_out, double* eri_out,
+                               ifci_stream_t stream) {
+  if (!h || !eri || !vir || !col_orb || !rot || !work || !h_out || !eri_out || n_orb < 1 || n_orb > 64 ||
+      n_vir < 1 || n_vir > 16 || n_s < 1 || n_other < 0 || n_keep < 0 || n_keep > n_vir ||
+      n_s + n_other + n_vir > n_orb) {
+    set_error("ifci_sno_transform: null pointer or inconsistent sizes");
+    return IFCI_ERR_ARG;
+  }
+  const int m = n_s + n_keep + n_other;
+  const int64_t n3m = (int64_t)n_orb * n_orb * n_orb * m;
+  if (work_doubles < (int64_t)n_orb * m + 2 * n3m) {
+    set_error("ifci_sno_transform: work holds " + std::to_string(work_doubles) + " doubles, needs " +
+              std::to_string((int64_t)n_orb * m + 2 * n3m));
+    return IFCI_ERR_ARG;
+  }
+  double* C = work;
+  double* b0 = work + (int64_t)n_orb * m;
+  double* b1 = b0 + n3m;
+  HIP_TRY(launch_sno_transform(h, eri, n_orb, vir, n_vir, col_orb, n_s, n_other, rot, n_keep, C, b0, b1, h_out,
+                               eri_out, (hipStream_t)stream),
+          "ifci_sno_transform");
+  return IFCI_OK;
+}
+
 ifci_status ifci_vector(ifci_plan_t p, int64_t inc, double* c_out, ifci_stream_t stream) {
   if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
   if (inc < 0 || inc >= (int64_t)p->inc.size() || !c_out) {

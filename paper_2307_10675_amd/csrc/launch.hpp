@@ -111,6 +111,13 @@ hipError_t launch_energy_screened(const double* e_inc, const int32_t* status, co
                                   hipStream_t st);
 hipError_t launch_mark_screened(const uint8_t* keep, int64_t first, int64_t count, double* e_out,
                                 int32_t* status_out, int32_t* iters_out, double* resid_out, hipStream_t st);
+hipError_t launch_sno_orbitals(const double* gamma, int n_orb, const int32_t* vir, int n_vir, const int32_t* inc_occ,
+                               int64_t n_inc, int order, double thresh, double* rot, int32_t* n_keep,
+                               hipStream_t st);
+hipError_t launch_sno_transform(const double* h, const double* eri, int n_orb, const int32_t* vir, int n_vir,
+                                const int32_t* col_orb, int n_s, int n_other, const double* rot, int n_keep,
+                                double* C, double* buf0, double* buf1, double* h_out, double* eri_out,
+                                hipStream_t st);
 hipError_t launch_energy(const double* e_inc, const int32_t* status, const int32_t* sub_ptr,
                          const int32_t* sub_idx, const int32_t* inc_size, int n_inc, int order,
                          const double* misc_in, double* eps, double* out, int32_t* bad,

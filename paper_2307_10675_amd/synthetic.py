@@ -176,6 +176,38 @@ def local_chain(n_bodies: int, seed: int = 0, order: int = 1, rate: float = 1.0,
                              n_chol=n_chol))
 
 
+class SnoProblem:
+    """Occupied orbitals (each a body, doubly occupied in the reference) and
+    virtual orbitals shared by every body, over one set of integrals."""
+
+    def __init__(self, h, eri, occ, vir, order, e_const=0.0, meta=None):
+        self.h, self.eri = h, eri
+        self.occ, self.vir = list(occ), list(vir)
+        self.order = order
+        self.e_const = e_const
+        self.n_orb = h.shape[0]
+        self.meta = meta or {}
+
+    def sha256(self) -> str:
+        m = hashlib.sha256()
+        m.update(np.ascontiguousarray(self.h).tobytes())
+        m.update(np.ascontiguousarray(self.eri).tobytes())
+        m.update(repr((self.occ, self.vir, self.order, self.e_const)).encode())
+        return m.hexdigest()
+
+
+def sno_system(n_occ: int, n_vir: int, seed: int, order: int = 2, n_chol: int = 12) -> SnoProblem:
+    """Integrals as in the module docstring (no decay) over n_occ + n_vir
+    orbitals; the n_occ orbitals of lowest h_pp (ties by index) are
+    occupied, the others virtual."""
+    n = n_occ + n_vir
+    h, eri = integrals(n, n_chol, seed)
+    ranked = sorted(range(n), key=lambda p: (h[p, p], p))
+    occ, vir = sorted(ranked[:n_occ]), sorted(ranked[n_occ:])
+    return SnoProblem(h, eri, occ, vir, order, meta=dict(kind="sno", n_occ=n_occ, n_vir=n_vir, seed=seed,
+                                                         n_chol=n_chol))
+
+
 def random_vector(n: int, seed: int, symmetric_dim: int | None = None) -> np.ndarray:
     """Seeded N(0,1) vector; with symmetric_dim = m it is reshaped to m x m
     and symmetrised (C = C^T), then flattened row-major."""

@@ -173,3 +173,17 @@ def test_screen_needs_solved_plan(L):
     assert L.ifci_screen(a._h, ctypes.c_void_p(256), 1e-4, None, ctypes.byref(n), None) == 6
     assert L.ifci_screen(None, ctypes.c_void_p(256), 1e-4, None, ctypes.byref(n), None) == 1
     a.close()
+
+
+def test_sno_argument_checks(L):
+    """The SNO entry points refuse bad sizes and a short work buffer before
+    any device work."""
+    import ctypes
+    d = ctypes.c_void_p(256)
+    assert L.ifci_sno_orbitals(d, 12, d, 17, d, 4, 2, 3.0, d, d, None) == 1      # n_vir > 16
+    assert L.ifci_sno_orbitals(None, 12, d, 8, d, 4, 2, 3.0, d, d, None) == 1
+    # m = 2 + 8 + 2 = 12 orbitals of 12: needs 12 * 12 + 2 * 12^4 doubles
+    need = 12 * 12 + 2 * 12 ** 4
+    assert L.ifci_sno_transform(d, d, 12, d, 8, d, 2, 2, d, 8, d, need - 1, d, d, None) == 1
+    assert L.ifci_sno_transform(d, d, 12, d, 8, d, 2, 2, d, 9, d, need, d, d, None) == 1   # n_keep > n_vir
+    assert L.ifci_sno_transform(d, d, 12, d, 8, d, 3, 2, d, 8, d, need, d, d, None) == 1   # too many orbitals
