@@ -21,6 +21,8 @@ Legs (--legs, comma separated; default all):
   large  14o14e / 16o16e: symmetric-sector sigma and whole solves
   w3     12 bodies, order 5 (1585 increments incl. 792 x 10o10e) and its gradient
   w4     256 independent 10o10e problems (K = 20, seeds 4000..4255)
+  cnb    connected n-body screening at 10^-4.6 Eh on a decaying 10-body chain
+  sno    summation natural orbitals: 6 occupied + 12 virtuals, order 3
   cpu    the oracle on the host cores
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs mixed,fp64,...]
@@ -44,7 +46,7 @@ PEAK = {"fp64_mfma": 78.6e12, "fp32_mfma": 157.3e12, "hbm": 8.0e12}
 KERNEL_SOURCES = ["batched.hip", "pspace.hpp", "device_common.hpp", "ifci_internal.h", "launch.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batched_lobpcg_kernel_workload2.traffic.json")
 ORACLE_W2 = os.path.join(ROOT, "tests", "golden", "oracle_w2.json")
-ALL_LEGS = ("mixed", "fp64", "plain", "large", "w3", "w4", "cpu")
+ALL_LEGS = ("mixed", "fp64", "plain", "large", "w3", "w4", "cnb", "sno", "cpu")
 
 TOL_UEH = 1e-6
 # One FP64 acceptance test for every leg: converged when the FP64 residual
@@ -353,6 +355,61 @@ def workload4_batch_leg(torch, ifci, synthetic, count=256):
             "sigma_tflops_over_solve": flops / wall / 1e12}
 
 
+def screening_leg(torch, ifci, synthetic):
+    """Connected n-body screening at the paper's parameter (10^-4.6 Eh) on a
+    10-body chain whose pair increments fall off with distance (order 4, 385
+    increments), mixed precision: kept increments per order and the time
+    against the unscreened expansion of the same problem."""
+    p = synthetic.local_chain(10, seed=5100, order=4, rate=1.0)
+    C = 10 ** -4.6
+    out = {"problem": "10 bodies x (2o, 2e), pair correlation decaying with distance, order 4: 385 increments",
+           "threshold_Eh": C}
+    kw = dict(precision=ifci.MIXED, r_tol=R_TOL, r_tol_inner=R_TOL_INNER, max_iter=600)
+    for name in ("full", "screened"):
+        for rep in range(2):  # the second run is timed
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            if name == "full":
+                plan, res = ifci.solve(p, **kw)
+            else:
+                plan, res = ifci.solve_screened(p, C, **kw)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t
+            plan.close()
+        sizes = [len(i) for i in synthetic_increments(p.n_bodies, p.order)]
+        entry = {"seconds": wall, "total": res["total"]}
+        if name == "screened":
+            keep = res["keep"]
+            entry["kept_by_order"] = [int(sum(1 for s, k in zip(sizes, keep) if k and s == n)) for n in range(1, 5)]
+            entry["increments_by_order"] = [sizes.count(n) for n in range(1, 5)]
+        out[name] = entry
+    out["total_change_Eh"] = out["screened"]["total"] - out["full"]["total"]
+    return out
+
+
+def synthetic_increments(n_bodies, order):
+    import itertools
+    return [S for k in range(1, order + 1) for S in itertools.combinations(range(n_bodies), k)]
+
+
+def sno_leg(torch, ifci, synthetic):
+    """SNO expansion: 6 occupied orbitals sharing 12 virtuals, order 3 (41
+    increments), natural orbitals kept above 10^-4, mixed precision; seconds
+    per step and the kept natural-orbital counts."""
+    from paper_2307_10675_amd.sno import solve_sno
+    p = synthetic.sno_system(6, 12, seed=8300, order=3)
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = solve_sno(p, 4.0, precision=ifci.MIXED, r_tol=R_TOL, r_tol_inner=R_TOL_INNER, max_iter=600)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+    nk = [int(x) for x in res["n_keep"]]
+    return {"problem": "6 occupied + 12 virtual orbitals, order 3: 41 increments, eta 4", "seconds": wall,
+            "seconds_by_step": res["seconds_by_step"], "all_converged": bool(res["converged"]),
+            "kept_virtuals_min_mean_max": [min(nk), sum(nk) / len(nk), max(nk)], "total": res["total"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -484,6 +541,10 @@ def main():
         out_detail["workload3_order5"] = workload3_leg(torch, ifci, synthetic)
     if "w4" in legs:
         out_detail["workload4_batch_10o10e"] = workload4_batch_leg(torch, ifci, synthetic)
+    if "cnb" in legs:
+        out_detail["cnb_screening"] = screening_leg(torch, ifci, synthetic)
+    if "sno" in legs:
+        out_detail["sno"] = sno_leg(torch, ifci, synthetic)
 
     head = mixed or fp64 or plain
     out = {
