@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define IFCI_ABI_VERSION 3
+#define IFCI_ABI_VERSION 4
 
 typedef struct ifci_plan_s* ifci_plan_t;
 typedef void* ifci_stream_t; /* a hipStream_t; NULL = the null stream */
@@ -389,6 +389,85 @@ ifci_status ifci_set_phase_counters(ifci_plan_t plan, int64_t* counters, int64_t
  * built-in choice.  IFCI_ERR_ARG outside k 1..8, ps_block -1..64,
  * e_waves 0..8. */
 ifci_status ifci_set_tuning(ifci_plan_t plan, int32_t k, int32_t precision, int32_t ps_block, int32_t e_waves);
+
+/* ---------------------------------------------------------------------------
+ * Heat-bath selected CI with a second-order Epstein-Nesbet correction (HBCI;
+ * paper, Methods, iFCI subsection, the HBCI paragraph, where it is the
+ * solver of every increment; the method of Holmes, Tubman and Umrigar,
+ * J. Chem. Theory Comput. 12, 3674 (2016)), on one increment of a plan whose
+ * integrals are set (ifci_set_integrals).
+ *
+ * Determinant keys (uint64): bit p (0 <= p < k) is the increment's p-th
+ * active orbital (ascending orbital index) with spin alpha, bit 32 + p the
+ * same orbital with spin beta.  The core's creation operators come first,
+ * then the alpha ones, then the beta ones, each group ascending; vectors over
+ * keys follow that sign convention.
+ *
+ * Selection: V starts as the reference determinant (the increment's closed
+ * shell) with c = 1; each step adds every determinant a outside V with
+ * max over i in V of |H_ai c_i| > eps1, together with its spin-flipped
+ * partner (alpha and beta strings exchanged), and re-solves the lowest root
+ * of H over V in the flip-symmetric sector (Davidson, restarted from the
+ * previous vector); it ends when a step adds nothing (converged) or after
+ * max_iter steps.  PT2: for every a outside V,
+ * N_a = sum over i in V with |H_ai c_i| > eps2 of H_ai c_i and
+ * E_PT2 = sum_a N_a^2 / (E_var - H_aa).  Every step runs in device kernels
+ * over hash tables in the caller's work buffer; the host drives the loop.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  double eps1;       /* variational selection threshold (Eh), >= 0 */
+  double eps2;       /* PT2 screening threshold (Eh), >= 0 */
+  int32_t max_iter;  /* selection steps, >= 1 */
+  int32_t max_dav;   /* Davidson iterations per step, >= 1 */
+  int32_t m_max;     /* Davidson subspace before a restart, 2..16 */
+  double r_tol;      /* a variational root is taken at ||H c - E c|| <= r_tol */
+  int64_t max_det;   /* capacity of V (determinants), >= 2 */
+  int64_t max_nnz;   /* capacity of H over V (off-diagonal nonzeros), >= 1 */
+  int64_t max_ext;   /* capacity of the PT2 external space, >= 1 */
+} ifci_hbci_options;
+
+/* The paper's thresholds (eps1 = 1 mEh, eps2 = 1 uEh) and capacities of
+ * 2^20 determinants, 2^28 nonzeros and 2^26 external determinants. */
+void ifci_hbci_default_options(ifci_hbci_options* options);
+
+/* Bytes of the device work buffer that the HBCI calls on increment inc need
+ * with these capacities (256-byte aligned buffer). */
+ifci_status ifci_hbci_work_bytes(ifci_plan_t plan, int64_t inc, const ifci_hbci_options* options,
+                                 int64_t* bytes);
+
+/* HBCI of increment inc.  result: host [8] = E_var (total energy, the
+ * plan's e_const and the frozen core included), E_PT2, |V|, selection steps
+ * taken, converged (1 when a step added nothing and every root met r_tol,
+ * else 0), the final residual norm, the number of external determinants
+ * with a nonzero N_a, and the nonzeros of H over V.  dets_out (device
+ * [max_det] keys, insertion order) and c_out (device [max_det], unit norm)
+ * receive V and its vector when non-NULL.  work: device [work_bytes] from
+ * ifci_hbci_work_bytes, 256-byte aligned, owned by the caller.  Synchronises
+ * the stream.  IFCI_ERR_OOM when V, H or the external space outgrow their
+ * capacities (the results are then not written); IFCI_ERR_ARG for bad
+ * options or a buffer too small; IFCI_ERR_STATE before ifci_set_integrals. */
+ifci_status ifci_hbci_solve(ifci_plan_t plan, int64_t inc, const ifci_hbci_options* options, void* work,
+                            int64_t work_bytes, double* result, uint64_t* dets_out, double* c_out,
+                            ifci_stream_t stream);
+
+/* The steps of ifci_hbci_solve on a caller's space, for checking them.
+ * dets: device [n] distinct keys (n <= max_det); c: device [n].
+ * ifci_hbci_sigma: sigma (device [n]) = (H - E_core - e_const) c over the
+ * space, the constant energy left out as in ifci_sigma.
+ * ifci_hbci_select: the keys added by one selection step from (dets, c) at
+ * eps1, flip partners included, into added (device [max_det - n], in no
+ * particular order) and their count into *n_added (host).
+ * ifci_hbci_pt2: *e_pt2 and *n_ext (host) of the PT2 step at eps2 about the
+ * total energy e_var.  All synchronise the stream; IFCI_ERR_OOM as above. */
+ifci_status ifci_hbci_sigma(ifci_plan_t plan, int64_t inc, const ifci_hbci_options* options, void* work,
+                            int64_t work_bytes, const uint64_t* dets, int64_t n, const double* c, double* sigma,
+                            ifci_stream_t stream);
+ifci_status ifci_hbci_select(ifci_plan_t plan, int64_t inc, const ifci_hbci_options* options, void* work,
+                             int64_t work_bytes, const uint64_t* dets, int64_t n, const double* c, double eps1,
+                             uint64_t* added, int64_t* n_added, ifci_stream_t stream);
+ifci_status ifci_hbci_pt2(ifci_plan_t plan, int64_t inc, const ifci_hbci_options* options, void* work,
+                          int64_t work_bytes, const uint64_t* dets, int64_t n, const double* c, double e_var,
+                          double eps2, double* e_pt2, int64_t* n_ext, ifci_stream_t stream);
 
 const char* ifci_status_string(ifci_status s);
 const char* ifci_last_error(void);

@@ -99,18 +99,11 @@ def select(H: np.ndarray, V: list[int], c: np.ndarray, eps1: float, flip_idx: np
     partners, in increasing list order."""
     inV = np.zeros(H.shape[0], dtype=bool)
     inV[V] = True
-    out = set()
-    for a in range(H.shape[0]):
-        if inV[a]:
-            continue
-        for t, i in enumerate(V):
-            if abs(H[a, i] * c[t]) > eps1:
-                out.add(a)
-                break
-    for a in list(out):
-        f = int(flip_idx[a])
-        if not inV[f]:
-            out.add(f)
+    outside = np.flatnonzero(~inV)
+    couple = np.abs(H[np.ix_(outside, V)] * c[None, :])       # |H_ai c_i|, a outside V
+    hit = outside[(couple > eps1).any(axis=1)]
+    out = set(int(a) for a in hit)
+    out |= {int(flip_idx[a]) for a in hit if not inV[flip_idx[a]]}
     return sorted(out)
 
 
@@ -118,18 +111,17 @@ def pt2(H: np.ndarray, V: list[int], c: np.ndarray, e_var: float, eps2: float):
     """(E_PT2, number of external determinants with a nonzero N_a)."""
     inV = np.zeros(H.shape[0], dtype=bool)
     inV[V] = True
+    outside = np.flatnonzero(~inV)
+    hc = H[np.ix_(outside, V)] * c[None, :]                   # H_ai c_i
+    keep = np.abs(hc) > eps2
     terms = []
-    n_ext = 0
-    for a in range(H.shape[0]):
-        if inV[a]:
-            continue
-        parts = [H[a, i] * c[t] for t, i in enumerate(V) if abs(H[a, i] * c[t]) > eps2]
-        if not parts:
+    for row, a in enumerate(outside):
+        parts = hc[row, keep[row]]
+        if parts.size == 0:
             continue
         n_a = math.fsum(parts)
-        n_ext += 1
         terms.append(n_a * n_a / (e_var - H[a, a]))
-    return math.fsum(terms), n_ext
+    return math.fsum(terms), len(terms)
 
 
 def solve(space: Space, eps1: float, eps2: float, max_iter: int = 32):

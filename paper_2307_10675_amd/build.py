@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libifci.so")
 
-SOURCES = ["plan.cpp", "abi.cpp", "embed.hip", "batched.hip", "plain.hip", "wide.hip", "energy.hip", "rdm.hip", "sno.hip"]
+SOURCES = ["plan.cpp", "abi.cpp", "embed.hip", "batched.hip", "plain.hip", "wide.hip", "energy.hip", "rdm.hip", "sno.hip", "hbci.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("IFCI_OFFLOAD_ARCH", "gfx950")

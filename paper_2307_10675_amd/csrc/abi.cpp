@@ -433,6 +433,55 @@ ifci_status launch_on_chip(ifci_plan_s* p, const std::vector<int32_t>& ids, int6
   return IFCI_OK;
 }
 
+// Validated HBCI call on increment inc: the increment's description for
+// the kernels, with the reference key from the host orbital lists.
+ifci_status hbci_setup(ifci_plan_t p, int64_t inc, const ifci_hbci_options* o, void* work, int64_t work_bytes,
+                       HbciInc* I) {
+  if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
+  if (inc < 0 || inc >= (int64_t)p->inc.size() || !o) {
+    set_error("HBCI: bad increment index or null options");
+    return IFCI_ERR_ARG;
+  }
+  if (!(o->eps1 >= 0.0) || !(o->eps2 >= 0.0) || !std::isfinite(o->eps1) || !std::isfinite(o->eps2) ||
+      o->max_iter < 1 || o->max_dav < 1 || o->m_max < 2 || o->m_max > 16 || !(o->r_tol > 0.0) || o->max_det < 2 ||
+      o->max_det > ((int64_t)1 << 30) || o->max_nnz < 1 || o->max_ext < 1 || o->max_ext > ((int64_t)1 << 40)) {
+    set_error("HBCI: options out of range (eps >= 0, max_iter, max_dav >= 1, 2 <= m_max <= 16, r_tol > 0, "
+              "2 <= max_det <= 2^30, max_nnz, max_ext >= 1)");
+    return IFCI_ERR_ARG;
+  }
+  ifci_status s = need_ints(p);
+  if (s != IFCI_OK) return s;
+  const IncDev& d = p->inc[inc];
+  if (!work || ((uintptr_t)work & 255u) || work_bytes < hbci_work_bytes(d.k, *o)) {
+    set_error("HBCI: work must be non-null, 256-byte aligned and at least ifci_hbci_work_bytes long");
+    return IFCI_ERR_ARG;
+  }
+  uint32_t ref = 0;
+  for (int i = 0; i < d.k; ++i) {
+    const int orb = p->orbs[d.act_off + i];
+    if (std::binary_search(p->ref_occ.begin(), p->ref_occ.end(), orb)) ref |= 1u << i;
+  }
+  I->h = p->h;
+  I->eri = p->eri;
+  I->n_orb = p->n_orb;
+  I->act = p->d_orbs + d.act_off;
+  I->k = d.k;
+  I->core = p->d_orbs + d.core_off;
+  I->n_core = d.n_core;
+  I->ref = (uint64_t)ref | ((uint64_t)ref << 32);
+  I->e_core = p->ws_ints() + d.int_off + int_block(d.k).misc;
+  I->e_const = p->e_const;
+  return IFCI_OK;
+}
+
+ifci_status hbci_space_args(const ifci_hbci_options* o, const uint64_t* dets, int64_t n, const double* c) {
+  if (!dets || !c || n < 1 || n > o->max_det) {
+    set_error("HBCI: need non-null dets and c and 1 <= n <= max_det");
+    return IFCI_ERR_ARG;
+  }
+  return IFCI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1139,6 +1188,87 @@ ifci_status ifci_sno_transform(const double* h, const double* eri, int32_t n_orb
                                eri_out, (hipStream_t)stream),
           "ifci_sno_transform");
   return IFCI_OK;
+}
+
+void ifci_hbci_default_options(ifci_hbci_options* o) {
+  if (!o) return;
+  o->eps1 = 1e-3;
+  o->eps2 = 1e-6;
+  o->max_iter = 32;
+  o->max_dav = 200;
+  o->m_max = 12;
+  o->r_tol = 1e-6;
+  o->max_det = (int64_t)1 << 20;
+  o->max_nnz = (int64_t)1 << 28;
+  o->max_ext = (int64_t)1 << 26;
+}
+
+ifci_status ifci_hbci_work_bytes(ifci_plan_t p, int64_t inc, const ifci_hbci_options* o, int64_t* bytes) {
+  if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
+  if (inc < 0 || inc >= (int64_t)p->inc.size() || !o || !bytes || o->max_det < 2 || o->max_nnz < 1 ||
+      o->max_ext < 1 || o->m_max < 2 || o->m_max > 16) {
+    set_error("ifci_hbci_work_bytes: bad increment, options or pointer");
+    return IFCI_ERR_ARG;
+  }
+  *bytes = hbci_work_bytes(p->inc[inc].k, *o);
+  return IFCI_OK;
+}
+
+ifci_status ifci_hbci_solve(ifci_plan_t p, int64_t inc, const ifci_hbci_options* o, void* work, int64_t work_bytes,
+                            double* result, uint64_t* dets_out, double* c_out, ifci_stream_t stream) {
+  HbciInc I;
+  ifci_status s = hbci_setup(p, inc, o, work, work_bytes, &I);
+  if (s != IFCI_OK) return s;
+  if (!result) {
+    set_error("ifci_hbci_solve: null result");
+    return IFCI_ERR_ARG;
+  }
+  DeviceGuard g(p->device);
+  return hbci_solve(I, *o, work, result, dets_out, c_out, (hipStream_t)stream);
+}
+
+ifci_status ifci_hbci_sigma(ifci_plan_t p, int64_t inc, const ifci_hbci_options* o, void* work, int64_t work_bytes,
+                            const uint64_t* dets, int64_t n, const double* c, double* sigma, ifci_stream_t stream) {
+  HbciInc I;
+  ifci_status s = hbci_setup(p, inc, o, work, work_bytes, &I);
+  if (s != IFCI_OK) return s;
+  if ((s = hbci_space_args(o, dets, n, c)) != IFCI_OK) return s;
+  if (!sigma || sigma == c) {
+    set_error("ifci_hbci_sigma: sigma must be non-null and distinct from c");
+    return IFCI_ERR_ARG;
+  }
+  DeviceGuard g(p->device);
+  return hbci_sigma(I, *o, work, dets, n, c, sigma, (hipStream_t)stream);
+}
+
+ifci_status ifci_hbci_select(ifci_plan_t p, int64_t inc, const ifci_hbci_options* o, void* work, int64_t work_bytes,
+                             const uint64_t* dets, int64_t n, const double* c, double eps1, uint64_t* added,
+                             int64_t* n_added, ifci_stream_t stream) {
+  HbciInc I;
+  ifci_status s = hbci_setup(p, inc, o, work, work_bytes, &I);
+  if (s != IFCI_OK) return s;
+  if ((s = hbci_space_args(o, dets, n, c)) != IFCI_OK) return s;
+  if (!added || !n_added || !(eps1 >= 0.0)) {
+    set_error("ifci_hbci_select: null output or eps1 < 0");
+    return IFCI_ERR_ARG;
+  }
+  DeviceGuard g(p->device);
+  return hbci_select(I, *o, work, dets, n, c, eps1, added, n_added, (hipStream_t)stream);
+}
+
+ifci_status ifci_hbci_pt2(ifci_plan_t p, int64_t inc, const ifci_hbci_options* o, void* work, int64_t work_bytes,
+                          const uint64_t* dets, int64_t n, const double* c, double e_var, double eps2, double* e_pt2,
+                          int64_t* n_ext, ifci_stream_t stream) {
+  HbciInc I;
+  ifci_status s = hbci_setup(p, inc, o, work, work_bytes, &I);
+  if (s != IFCI_OK) return s;
+  if ((s = hbci_space_args(o, dets, n, c)) != IFCI_OK) return s;
+  if (!e_pt2 || !n_ext || !(eps2 >= 0.0) || !std::isfinite(e_var)) {
+    set_error("ifci_hbci_pt2: null output, eps2 < 0 or e_var not finite");
+    return IFCI_ERR_ARG;
+  }
+  DeviceGuard g(p->device);
+  return hbci_pt2(I, *o, work, dets, n, c, e_var, eps2, e_pt2, n_ext, (hipStream_t)stream);
 }
 
 ifci_status ifci_vector(ifci_plan_t p, int64_t inc, double* c_out, ifci_stream_t stream) {

@@ -131,4 +131,31 @@ hipError_t launch_rdm_accumulate(const IncDev* incs, int n_inc, const int32_t* o
                                  const double* w, const int32_t* ref_occ, int n_ref, int n,
                                  double* dh, double* deri, hipStream_t st);
 
+// Heat-bath selected CI of one increment (hbci.hip).  The integrals are the
+// full h and eri with the increment's sorted active and core orbital lists
+// (device); ref is the reference determinant's key; e_core points at the
+// increment's frozen-core energy on the device; e_const is the problem's
+// constant.  Each call synchronises the stream.
+struct HbciInc {
+  const double* h;
+  const double* eri;
+  int n_orb;
+  const int32_t* act;
+  int k;
+  const int32_t* core;
+  int n_core;
+  uint64_t ref;
+  const double* e_core;
+  double e_const;
+};
+int64_t hbci_work_bytes(int k, const ifci_hbci_options& o);
+ifci_status hbci_solve(const HbciInc& I, const ifci_hbci_options& o, void* work, double* result, uint64_t* dets_out,
+                       double* c_out, hipStream_t st);
+ifci_status hbci_sigma(const HbciInc& I, const ifci_hbci_options& o, void* work, const uint64_t* dets, int64_t n,
+                       const double* c, double* sigma, hipStream_t st);
+ifci_status hbci_select(const HbciInc& I, const ifci_hbci_options& o, void* work, const uint64_t* dets, int64_t n,
+                        const double* c, double eps1, uint64_t* added, int64_t* n_added, hipStream_t st);
+ifci_status hbci_pt2(const HbciInc& I, const ifci_hbci_options& o, void* work, const uint64_t* dets, int64_t n,
+                     const double* c, double e_var, double eps2, double* e_pt2, int64_t* n_ext, hipStream_t st);
+
 }  // namespace ifci

@@ -38,6 +38,12 @@ class Options(ctypes.Structure):
                 ("flags", ctypes.c_uint32), ("n_guess", ctypes.c_int32)]
 
 
+class HbciOptions(ctypes.Structure):
+    _fields_ = [("eps1", ctypes.c_double), ("eps2", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("max_dav", ctypes.c_int32), ("m_max", ctypes.c_int32), ("r_tol", ctypes.c_double),
+                ("max_det", ctypes.c_int64), ("max_nnz", ctypes.c_int64), ("max_ext", ctypes.c_int64)]
+
+
 _lib = None
 
 _SIGNATURES = {
@@ -89,6 +95,24 @@ _SIGNATURES = {
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "ifci_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32]),
+    "ifci_hbci_default_options": (None, [ctypes.POINTER(HbciOptions)]),
+    "ifci_hbci_work_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(HbciOptions),
+                                            ctypes.POINTER(ctypes.c_int64)]),
+    "ifci_hbci_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(HbciOptions),
+                                       ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "ifci_hbci_sigma": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(HbciOptions),
+                                       ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "ifci_hbci_select": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(HbciOptions),
+                                        ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
+    "ifci_hbci_pt2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(HbciOptions),
+                                     ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                     ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.c_void_p]),
     "ifci_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ifci_last_error": (ctypes.c_char_p, []),
 }
@@ -139,6 +163,17 @@ def default_options(**kw) -> Options:
 
 
 TUNING_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+
+
+def hbci_options(**kw) -> HbciOptions:
+    """ifci_hbci_default_options with fields overridden by keyword."""
+    o = HbciOptions()
+    lib().ifci_hbci_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
 
 
 def load_tuning(path: str = TUNING_PATH):
@@ -365,6 +400,87 @@ class Plan:
             w = torch.as_tensor(weights, dtype=torch.float64, device=dev).contiguous()
         _check(lib().ifci_rdm(self._h, _ptr(w), _ptr(dh), _ptr(dg), _stream(stream)))
         return dh, dg
+
+
+    # ---------------------------------------------------------------- HBCI
+    def hbci_work(self, inc: int, opts: HbciOptions):
+        """A device work buffer for the HBCI calls on increment inc (torch,
+        256-byte aligned view): (tensor, pointer, bytes)."""
+        import torch
+        nb = ctypes.c_int64()
+        _check(lib().ifci_hbci_work_bytes(self._h, inc, ctypes.byref(opts), ctypes.byref(nb)))
+        buf = torch.empty(nb.value // 8 + 64, dtype=torch.float64, device=torch.device("cuda", self.device))
+        base = buf.data_ptr()
+        return buf, ctypes.c_void_p(base + (-base) % 256), nb.value
+
+    def hbci(self, inc: int, opts: HbciOptions | None = None, work=None, with_space: bool = False, stream=None):
+        """ifci_hbci_solve: dict(E_var, E_pt2, E, n_det, n_iter, converged,
+        residual, n_ext, nnz[, dets, c])."""
+        import torch
+        opts = opts or hbci_options()
+        work = work or self.hbci_work(inc, opts)
+        res = (ctypes.c_double * 8)()
+        dets = c = None
+        if with_space:
+            dev = torch.device("cuda", self.device)
+            dets = torch.empty(opts.max_det, dtype=torch.int64, device=dev)
+            c = torch.empty(opts.max_det, dtype=torch.float64, device=dev)
+        _check(lib().ifci_hbci_solve(self._h, inc, ctypes.byref(opts), work[1], work[2], res, _ptr(dets), _ptr(c),
+                                     _stream(stream)))
+        out = dict(E_var=res[0], E_pt2=res[1], E=res[0] + res[1], n_det=int(res[2]), n_iter=int(res[3]),
+                   converged=bool(res[4]), residual=res[5], n_ext=int(res[6]), nnz=int(res[7]))
+        if with_space:
+            out["dets"] = dets[: out["n_det"]]
+            out["c"] = c[: out["n_det"]]
+        return out
+
+    def hbci_sigma(self, inc: int, dets, c, opts: HbciOptions | None = None, work=None, stream=None):
+        import torch
+        opts = opts or hbci_options(max_det=max(2, len(dets)))
+        work = work or self.hbci_work(inc, opts)
+        dets, c = dets.contiguous(), c.contiguous()
+        out = torch.empty_like(c)
+        _check(lib().ifci_hbci_sigma(self._h, inc, ctypes.byref(opts), work[1], work[2], _ptr(dets), len(dets),
+                                     _ptr(c), _ptr(out), _stream(stream)))
+        return out
+
+    def hbci_select(self, inc: int, dets, c, eps1: float, opts: HbciOptions, work=None, stream=None):
+        import torch
+        work = work or self.hbci_work(inc, opts)
+        dets, c = dets.contiguous(), c.contiguous()
+        added = torch.empty(max(1, opts.max_det - len(dets)), dtype=torch.int64, device=dets.device)
+        n = ctypes.c_int64()
+        _check(lib().ifci_hbci_select(self._h, inc, ctypes.byref(opts), work[1], work[2], _ptr(dets), len(dets),
+                                      _ptr(c), eps1, _ptr(added), ctypes.byref(n), _stream(stream)))
+        return added[: n.value]
+
+    def hbci_pt2(self, inc: int, dets, c, e_var: float, eps2: float, opts: HbciOptions, work=None, stream=None):
+        work = work or self.hbci_work(inc, opts)
+        dets, c = dets.contiguous(), c.contiguous()
+        e2, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().ifci_hbci_pt2(self._h, inc, ctypes.byref(opts), work[1], work[2], _ptr(dets), len(dets),
+                                   _ptr(c), e_var, eps2, ctypes.byref(e2), ctypes.byref(n), _stream(stream)))
+        return e2.value, n.value
+
+    def hbci_expansion(self, opts: HbciOptions | None = None, stream=None):
+        """Every increment by HBCI (E = E_var + E_PT2), then the energy sums
+        of eqs. 1-5: dict(results, energy, seconds)."""
+        import time
+
+        import torch
+        opts = opts or hbci_options()
+        dev = torch.device("cuda", self.device)
+        t0 = time.perf_counter()
+        by_k, results = {}, []
+        for i in range(self.n_inc):
+            k = self.increment(i).n_act
+            if k not in by_k:
+                by_k[k] = self.hbci_work(i, opts)
+            results.append(self.hbci(i, opts, work=by_k[k], stream=stream))
+        E = torch.tensor([r["E"] for r in results], dtype=torch.float64, device=dev)
+        st = torch.tensor([1 if r["converged"] else 2 for r in results], dtype=torch.int32, device=dev)
+        en = self.energy(E, st, stream=stream)
+        return dict(results=results, energy=en, seconds=time.perf_counter() - t0)
 
 
 def davidson_group(plans, stream=None):

@@ -27,7 +27,7 @@ def test_exports_every_declared_symbol(L):
     assert len(names) >= 15
     for n in sorted(names):
         assert hasattr(L, n), n
-    assert L.ifci_abi_version() == 3
+    assert L.ifci_abi_version() == 4
 
 
 @pytest.mark.parametrize("k,n", [(k, n) for k in range(1, 13) for n in range(0, k + 1)])
@@ -187,3 +187,33 @@ def test_sno_argument_checks(L):
     assert L.ifci_sno_transform(d, d, 12, d, 8, d, 2, 2, d, 8, d, need - 1, d, d, None) == 1
     assert L.ifci_sno_transform(d, d, 12, d, 8, d, 2, 2, d, 9, d, need, d, d, None) == 1   # n_keep > n_vir
     assert L.ifci_sno_transform(d, d, 12, d, 8, d, 3, 2, d, 8, d, need, d, d, None) == 1   # too many orbitals
+
+
+def test_hbci_options_and_argument_checks(L):
+    """The HBCI entry points: the paper's thresholds as defaults, the work
+    size growing with the capacities, and refusals before any device work
+    (bad options, no integrals, a short or misaligned buffer)."""
+    import ctypes
+    from paper_2307_10675_amd import ifci, synthetic
+    o = ifci.hbci_options()
+    assert (o.eps1, o.eps2) == (1e-3, 1e-6)
+    assert 2 <= o.m_max <= 16 and o.max_iter >= 1 and o.max_det >= 2
+    p = synthetic.chain(3, seed=1, order=2)
+    a = ifci.Plan(p, tuning=None)
+    small = ifci.hbci_options(max_det=64, max_nnz=1024, max_ext=256)
+    big = ifci.hbci_options(max_det=128, max_nnz=1024, max_ext=256)
+    nb_s, nb_b = ctypes.c_int64(), ctypes.c_int64()
+    assert L.ifci_hbci_work_bytes(a._h, 3, ctypes.byref(small), ctypes.byref(nb_s)) == 0
+    assert L.ifci_hbci_work_bytes(a._h, 3, ctypes.byref(big), ctypes.byref(nb_b)) == 0
+    assert 0 < nb_s.value < nb_b.value
+    assert L.ifci_hbci_work_bytes(a._h, 99, ctypes.byref(small), ctypes.byref(nb_s)) == 1
+    bad = ifci.hbci_options(max_det=64, max_nnz=1024, max_ext=256, m_max=17)
+    assert L.ifci_hbci_work_bytes(a._h, 0, ctypes.byref(bad), ctypes.byref(nb_s)) == 1
+    res = (ctypes.c_double * 8)()
+    w = ctypes.c_void_p(1 << 20)
+    # bad options first, then the missing integrals
+    neg = ifci.hbci_options(max_det=64, max_nnz=1024, max_ext=256, eps1=-1.0)
+    assert L.ifci_hbci_solve(a._h, 0, ctypes.byref(neg), w, 1 << 30, res, None, None, None) == 1
+    assert L.ifci_hbci_solve(a._h, 0, ctypes.byref(small), w, 1 << 30, res, None, None, None) == 6
+    assert L.ifci_hbci_solve(None, 0, ctypes.byref(small), w, 1 << 30, res, None, None, None) == 1
+    a.close()

@@ -1,0 +1,195 @@
+"""HBCI on the device (ifci_hbci_*) against the oracle (oracle/hbci.py).
+
+Each step is compared on identical inputs: H c over a given determinant list
+against the oracle's Slater-Condon matrix (1e-12 relative), one selection
+step from the oracle's space and vector (the same keys, bit for bit, after
+checking that no coupling lies within 1e-9 of eps1), the PT2 energy from the
+oracle's space, vector and energy (1e-11).  The whole solve is compared on
+6o6e and 8o8e increments: the same space (as sets), the same number of
+steps, E_var and E_PT2 within 1e-9.  eps1 = 0 gives the exact increment
+energy of the FCI solver; the HBCI expansion of eqs. 1-5 matches the oracle's
+sums.  Keys and vectors are converted between the oracle's full-space
+determinants and the library's active-space keys with the core-first phases.
+"""
+import numpy as np
+import pytest
+
+from oracle import fci, hbci, ifci as oifci
+from paper_2307_10675_amd import synthetic
+from tests.helpers import active_hamiltonian, gpu_available, string_phase
+
+pytestmark = pytest.mark.gpu
+
+if not gpu_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import torch  # noqa: E402
+
+from paper_2307_10675_amd import ifci  # noqa: E402
+
+DEV = torch.device("cuda", 0)
+
+
+def to_keys(problem, S, dets):
+    """(keys, phases) of full-space determinants in the library convention."""
+    active, core, _ = fci.increment_orbitals(problem.bodies, problem.nocc, S)
+    n = problem.n_orb
+    mask = (1 << n) - 1
+    keys, ph = [], []
+    for d in dets:
+        a, b = d & mask, d >> n
+        ka = sum(1 << i for i, p in enumerate(active) if a >> p & 1)
+        kb = sum(1 << i for i, p in enumerate(active) if b >> p & 1)
+        keys.append(ka | (kb << 32))
+        ph.append(string_phase(a, set(core)) * string_phase(b, set(core)))
+    return np.array(keys, dtype=np.int64), np.array(ph, dtype=np.float64)
+
+
+@pytest.fixture(scope="module")
+def chain4():
+    p = synthetic.chain(4, seed=7400, order=4)
+    plan = ifci.Plan(p, tuning=None).attach(p.h, p.eri)
+    index = {plan.increment(i).bodies: i for i in range(plan.n_inc)}
+    spaces = {S: hbci.Space(p, S) for S in [(0, 1), (0, 1, 2), (1, 2, 3)]}
+    return p, plan, index, spaces
+
+
+def small_opts(**kw):
+    base = dict(max_det=8192, max_nnz=1 << 22, max_ext=1 << 18, r_tol=1e-9, max_dav=400)
+    base.update(kw)
+    return ifci.hbci_options(**base)
+
+
+@pytest.mark.parametrize("S", [(0, 1), (0, 1, 2)])
+def test_sigma_over_a_list(chain4, S):
+    p, plan, index, spaces = chain4
+    sp = spaces[S]
+    Ha, _, s = active_hamiltonian(p, S)
+    keys, ph = to_keys(p, S, sp.dets)
+    assert np.array_equal(ph, s)
+    rng = np.random.default_rng(11)
+    for sub in (np.arange(len(keys)), np.sort(rng.choice(len(keys), size=len(keys) // 2, replace=False))):
+        c = rng.normal(size=len(sub))
+        got = plan.hbci_sigma(index[S], torch.tensor(keys[sub], device=DEV),
+                              torch.tensor(c, device=DEV)).cpu().numpy()
+        ref = Ha[np.ix_(sub, sub)] @ c
+        assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("eps1", [2e-2, 3e-3])
+def test_one_selection_step(chain4, eps1):
+    p, plan, index, spaces = chain4
+    S = (0, 1, 2)
+    sp = spaces[S]
+    V, c = [sp.ref], np.ones(1)
+    for _ in range(2):
+        V = V + hbci.select(sp.H, V, c, eps1, sp.flip)
+        _, c = hbci.lowest_in(sp.H, V, sp.flip)
+    outside = [a for a in range(len(sp.dets)) if a not in set(V)]
+    couple = np.abs(sp.H[np.ix_(outside, V)] * c[None, :])
+    assert np.abs(couple - eps1).min() > 1e-9          # no decision on the edge
+    new = hbci.select(sp.H, V, c, eps1, sp.flip)
+    assert new
+    keys, ph = to_keys(p, S, sp.dets)
+    opts = small_opts()
+    got = plan.hbci_select(index[S], torch.tensor(keys[V], device=DEV), torch.tensor(ph[V] * c, device=DEV),
+                           eps1, opts).cpu().numpy()
+    assert sorted(got.tolist()) == sorted(keys[new].tolist())
+
+
+@pytest.mark.parametrize("eps2", [0.0, 1e-5])
+def test_pt2_from_the_oracle_space(chain4, eps2):
+    p, plan, index, spaces = chain4
+    S = (0, 1, 2)
+    sp = spaces[S]
+    r = hbci.solve(sp, 5e-3, 0.0)
+    e2, n_ext = hbci.pt2(sp.H, r["V"], r["c"], r["E_var"], eps2)
+    keys, ph = to_keys(p, S, sp.dets)
+    opts = small_opts()
+    g2, gn = plan.hbci_pt2(index[S], torch.tensor(keys[r["V"]], device=DEV),
+                           torch.tensor(ph[r["V"]] * r["c"], device=DEV), r["E_var"], eps2, opts)
+    assert gn == n_ext
+    assert abs(g2 - e2) <= 1e-11 * max(1.0, abs(e2))
+
+
+@pytest.mark.parametrize("S,eps1", [((0, 1, 2), 5e-3), ((0, 1, 2), 1e-3), ((1, 2, 3), 2e-3)])
+def test_solve_against_the_oracle(chain4, S, eps1):
+    p, plan, index, spaces = chain4
+    sp = spaces[S]
+    ref = hbci.solve(sp, eps1, 1e-6)
+    got = plan.hbci(index[S], small_opts(eps1=eps1, eps2=1e-6), with_space=True)
+    keys, ph = to_keys(p, S, sp.dets)
+    assert got["converged"] and ref["converged"]
+    assert got["n_iter"] == ref["n_iter"]
+    assert sorted(got["dets"].cpu().numpy().tolist()) == sorted(keys[ref["V"]].tolist())
+    assert abs(got["E_var"] - ref["E_var"]) < 1e-9
+    assert abs(got["E_pt2"] - ref["E_pt2"]) < 1e-9
+    assert got["n_ext"] == ref["n_ext"]
+    # the vector: the oracle's up to sign, in the library's phases
+    pos = {int(k): t for t, k in enumerate(got["dets"].cpu().numpy())}
+    cg = got["c"].cpu().numpy()[[pos[int(k)] for k in keys[ref["V"]]]]
+    co = ph[ref["V"]] * ref["c"]
+    assert min(np.abs(cg - co).max(), np.abs(cg + co).max()) < 1e-7
+
+
+def test_eps1_zero_is_fci(chain4):
+    p, plan, index, spaces = chain4
+    S = (0, 1, 2)
+    e, st, _, _ = plan.davidson()
+    got = plan.hbci(index[S], small_opts(eps1=0.0, eps2=0.0))
+    assert got["converged"] and got["n_det"] == spaces[S].H.shape[0]
+    assert got["E_pt2"] == 0.0 and got["n_ext"] == 0
+    assert abs(got["E_var"] - float(e[index[S]])) < 1e-9
+    assert abs(got["E_var"] - fci.lowest_symmetric(spaces[S].H, spaces[S].n_str)[0]) < 1e-9
+
+
+def test_eight_orbital_increment_and_variational_order(chain4):
+    """The whole 4-body increment (8o8e): against the oracle at 1 mEh, and
+    E_var falling toward the exact energy as eps1 falls."""
+    p, plan, index, spaces = chain4
+    S = (0, 1, 2, 3)
+    sp = hbci.Space(p, S)
+    ref = hbci.solve(sp, 1e-3, 1e-6)
+    got = plan.hbci(index[S], small_opts(eps1=1e-3, eps2=1e-6), with_space=True)
+    keys, _ = to_keys(p, S, sp.dets)
+    assert got["converged"] and got["n_iter"] == ref["n_iter"]
+    assert sorted(got["dets"].cpu().numpy().tolist()) == sorted(keys[ref["V"]].tolist())
+    assert abs(got["E_var"] - ref["E_var"]) < 1e-9 and abs(got["E_pt2"] - ref["E_pt2"]) < 1e-9
+    exact = fci.lowest_symmetric(sp.H, sp.n_str)[0]
+    prev = None
+    for eps1 in (1e-2, 3e-3, 1e-3, 3e-4):
+        r = plan.hbci(index[S], small_opts(eps1=eps1, eps2=1e-6))
+        assert r["E_var"] >= exact - 1e-10
+        if prev is not None:
+            assert r["E_var"] <= prev + 1e-10
+        prev = r["E_var"]
+    assert abs(prev + r["E_pt2"] - exact) < 1e-4
+
+
+def test_hbci_expansion_matches_the_oracle(chain4):
+    p, plan, index, spaces = chain4
+    small = synthetic.chain(4, seed=7400, order=3)
+    pl = ifci.Plan(small, tuning=None).attach(small.h, small.eri)
+    out = pl.hbci_expansion(small_opts(eps1=2e-3, eps2=1e-6))
+    E = {}
+    for i in range(pl.n_inc):
+        S = pl.increment(i).bodies
+        E[S] = hbci.solve_increment(small, S, 2e-3, 1e-6)["E"]
+        assert abs(out["results"][i]["E"] - E[S]) < 1e-9
+    eps, by_order, total = oifci.increments_from_energies(E, oifci.reference_energy(small), small.order)
+    assert abs(out["energy"]["total"] - total) < 1e-8
+    for a, b in zip(out["energy"]["by_order"], by_order):
+        assert abs(a - b) < 1e-8
+    pl.close()
+
+
+def test_capacity_errors_are_reported(chain4):
+    p, plan, index, spaces = chain4
+    S = (0, 1, 2)
+    assert plan.hbci(index[S], small_opts(eps1=2e-2))["n_ext"] > 4
+    with pytest.raises(ifci.IfciError) as e:
+        plan.hbci(index[S], small_opts(eps1=1e-3, max_det=8))
+    assert e.value.code == 3
+    with pytest.raises(ifci.IfciError) as e:
+        plan.hbci(index[S], small_opts(eps1=2e-2, max_ext=4))
+    assert e.value.code == 3
