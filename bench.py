@@ -23,6 +23,7 @@ Legs (--legs, comma separated; default all):
   w4     256 independent 10o10e problems (K = 20, seeds 4000..4255)
   cnb    connected n-body screening at 10^-4.6 Eh on a decaying 10-body chain
   sno    summation natural orbitals: 6 occupied + 12 virtuals, order 3
+  hbci   heat-bath selected CI + EN-PT2 on a 16o16e increment against its FCI
   cpu    the oracle on the host cores
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs mixed,fp64,...]
@@ -46,7 +47,7 @@ PEAK = {"fp64_mfma": 78.6e12, "fp32_mfma": 157.3e12, "hbm": 8.0e12}
 KERNEL_SOURCES = ["batched.hip", "pspace.hpp", "device_common.hpp", "ifci_internal.h", "launch.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batched_lobpcg_kernel_workload2.traffic.json")
 ORACLE_W2 = os.path.join(ROOT, "tests", "golden", "oracle_w2.json")
-ALL_LEGS = ("mixed", "fp64", "plain", "large", "w3", "w4", "cnb", "sno", "cpu")
+ALL_LEGS = ("mixed", "fp64", "plain", "large", "w3", "w4", "cnb", "sno", "hbci", "cpu")
 
 TOL_UEH = 1e-6
 # One FP64 acceptance test for every leg: converged when the FP64 residual
@@ -410,6 +411,43 @@ def sno_leg(torch, ifci, synthetic):
             "kept_virtuals_min_mean_max": [min(nk), sum(nk) / len(nk), max(nk)], "total": res["total"]}
 
 
+def hbci_leg(torch, ifci, synthetic):
+    """HBCI (eps2 = 1 uEh) of one 16o16e increment (an 8-body decaying chain
+    taken as one body, 165,636,900 determinants) at eps1 = 1 mEh (the
+    paper's) and 3e-4, against the increment's exact energy from the FCI
+    path (mixed precision to residual 1e-5): seconds, |V|, nonzeros of H over
+    V, external determinants, errors of E_var and E_var + E_PT2."""
+    p = synthetic.merged(synthetic.chain(8, seed=4108, order=1))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plan, res = ifci.solve(p, precision=ifci.MIXED, r_tol=1e-5, r_tol_inner=1e-5, max_iter=400)
+    torch.cuda.synchronize()
+    fci_s = time.perf_counter() - t
+    e_fci = float(res["E"][0])
+    plan.close()
+    del plan, res
+    torch.cuda.empty_cache()
+    pl = ifci.Plan(p, tuning=None).attach(p.h, p.eri)
+    runs = []
+    for eps1 in (1e-3, 3e-4):
+        opts = ifci.hbci_options(eps1=eps1, eps2=1e-6, max_det=1 << 21, max_nnz=1 << 29, max_ext=1 << 26,
+                                 r_tol=1e-6)
+        work = pl.hbci_work(0, opts)
+        pl.hbci(0, opts, work=work)                 # warm-up (kernel attributes, staging)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = pl.hbci(0, opts, work=work)
+        secs = time.perf_counter() - t
+        runs.append(dict(eps1=eps1, seconds=round(secs, 4), n_det=r["n_det"], steps=r["n_iter"], nnz=r["nnz"],
+                         n_ext=r["n_ext"], converged=r["converged"], E_var=r["E_var"], E_pt2=r["E_pt2"],
+                         err_var_Eh=r["E_var"] - e_fci, err_total_Eh=r["E"] - e_fci))
+        del work
+        torch.cuda.empty_cache()
+    pl.close()
+    return dict(increment="16o16e (merged 8-body chain, seed 4108)", fci_seconds_mixed=round(fci_s, 3),
+                E_fci=e_fci, runs=runs)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -545,6 +583,8 @@ def main():
         out_detail["cnb_screening"] = screening_leg(torch, ifci, synthetic)
     if "sno" in legs:
         out_detail["sno"] = sno_leg(torch, ifci, synthetic)
+    if "hbci" in legs:
+        out_detail["hbci_16o16e"] = hbci_leg(torch, ifci, synthetic)
 
     head = mixed or fp64 or plain
     out = {

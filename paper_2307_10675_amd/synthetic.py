@@ -196,6 +196,15 @@ class SnoProblem:
         return m.hexdigest()
 
 
+def merged(p: Problem) -> Problem:
+    """The same integrals with every orbital in one body (the whole system as
+    a single increment): the bodies' occupied orbitals first, in body order,
+    then their virtual orbitals."""
+    occ = [o for b, orbs in enumerate(p.bodies) for o in orbs[: p.nocc[b]]]
+    vir = [o for b, orbs in enumerate(p.bodies) for o in orbs[p.nocc[b]:]]
+    return Problem(p.h, p.eri, [occ + vir], [len(occ)], 1, p.e_const, meta=dict(p.meta, merged=True))
+
+
 def sno_system(n_occ: int, n_vir: int, seed: int, order: int = 2, n_chol: int = 12) -> SnoProblem:
     """Integrals as in the module docstring (no decay) over n_occ + n_vir
     orbitals; the n_occ orbitals of lowest h_pp (ties by index) are

@@ -193,3 +193,49 @@ def test_capacity_errors_are_reported(chain4):
     with pytest.raises(ifci.IfciError) as e:
         plan.hbci(index[S], small_opts(eps1=2e-2, max_ext=4))
     assert e.value.code == 3
+
+
+def test_fourteen_orbitals_at_the_paper_thresholds():
+    """A 14o14e increment (a 7-body chain as one body, 11.8M determinants)
+    at eps1 = 1 mEh, eps2 = 1 uEh: the variational energy above the exact
+    one (FP64 FCI path), PT2 lowering it toward it, a space closed under the
+    flip with a unit, flip-symmetric vector; on sampled rows the oracle's
+    Slater-Condon (H c)_I over the returned space equals E_var c_I within
+    the residual tolerance, and the selection is at its fixed point: no
+    replacement J of a leading determinant with |H_JI c_I| > eps1 is missing."""
+    from oracle import hamiltonian
+    p = synthetic.merged(synthetic.chain(7, seed=4107, order=1))
+    n = p.n_orb
+    plan, res = ifci.solve(p, precision=ifci.FP64, r_tol=1e-7, max_iter=400)
+    e_fci = float(res["E"][0])
+    plan.close()
+    pl = ifci.Plan(p, tuning=None).attach(p.h, p.eri)
+    opts = ifci.hbci_options(eps1=1e-3, eps2=1e-6, max_det=1 << 19, max_nnz=1 << 28, max_ext=1 << 25, r_tol=1e-6)
+    r = pl.hbci(0, opts, with_space=True)
+    print(f"[hbci14] n_det {r['n_det']} steps {r['n_iter']} E_var {r['E_var']:.9f} E_pt2 {r['E_pt2']:.3e} "
+          f"fci {e_fci:.9f}", flush=True)
+    assert r["converged"]
+    assert r["E_var"] >= e_fci - 1e-9
+    assert r["E_pt2"] < 0.0 and abs(r["E"] - e_fci) < abs(r["E_var"] - e_fci)
+    keys = r["dets"].cpu().numpy()
+    c = r["c"].cpu().numpy()
+    assert len(set(keys.tolist())) == len(keys)
+    pos = {int(k): t for t, k in enumerate(keys)}
+    flip = np.array([pos[int((k >> 32) | ((k & 0xFFFFFFFF) << 32))] for k in keys])
+    assert abs(np.linalg.norm(c) - 1.0) < 1e-10 and np.abs(c[flip] - c).max() < 1e-10
+    ints = hamiltonian.SpinOrbitalIntegrals(p.h, p.eri)
+    full = lambda k: (int(k) & 0xFFFFFFFF) | ((int(k) >> 32) << n)
+    key_of = lambda d: (d & ((1 << n) - 1)) | ((d >> n) << 32)
+    rng = np.random.default_rng(3)
+    rows = list(rng.choice(len(keys), size=12, replace=False)) + list(np.argsort(-np.abs(c))[:4])
+    for I in rows:
+        d = full(keys[I])
+        acc = [(hamiltonian.diagonal(ints, d) + p.e_const - r["E_var"]) * c[I]]
+        conn = hamiltonian.connected(ints, d, list(range(n)))
+        acc += [v * c[pos[key_of(J)]] for J, v in conn if key_of(J) in pos]
+        assert abs(sum(acc)) <= 1e-6
+    for I in np.argsort(-np.abs(c))[:4]:
+        for J, v in hamiltonian.connected(ints, full(keys[I]), list(range(n))):
+            if abs(v * c[I]) > 1e-3 * (1 + 1e-9):
+                assert key_of(J) in pos
+    pl.close()
