@@ -83,6 +83,12 @@ __device__ __forceinline__ double phase(uint32_t s, int x, int y) {
 
 __host__ __device__ __forceinline__ uint64_t flip_key(uint64_t key) { return (key >> 32) | (key << 32); }
 
+// A flip pair's representative: the smaller of a key and its partner.  In
+// the solve path vectors are flip-symmetric (c_a = c_flip(a), and H commutes
+// with the flip), so only representatives are walked: a row of H, a
+// selection source or a PT2 source stands for its partner too.
+__device__ __forceinline__ bool canonical(uint64_t key) { return key <= flip_key(key); }
+
 // ---------------------------------------------------------------- hash tables
 
 __device__ __forceinline__ int32_t ht_find(const uint64_t* keys, const int32_t* vals, uint64_t mask, uint64_t key) {
@@ -418,14 +424,15 @@ __global__ void hbci_load_kernel(const uint64_t* __restrict__ in, int64_t n, uin
 // |H_ai c_i| > eps joins V, with its flip partner.
 __global__ void __launch_bounds__(64 * kWaves) hbci_select_kernel(const double* __restrict__ ints, int k,
                                                                   const double* __restrict__ c, int64_t n_src,
-                                                                  double eps, Space V) {
+                                                                  double eps, Space V, int half) {
   const Lds s = load_lds(ints, k);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint8_t* L = s.lists + wave * 64;
   for (int64_t i = (int64_t)blockIdx.x * kWaves + wave; i < n_src; i += (int64_t)gridDim.x * kWaves) {
     const double ci = c[i];
-    if (ci == 0.0) continue;
-    const Det d = make_det(V.dets[i], k, L, lane);
+    const uint64_t key = V.dets[i];
+    if (ci == 0.0 || (half && !canonical(key))) continue;
+    const Det d = make_det(key, k, L, lane);
     for (int t = lane; t < d.total; t += 64) {
       double v;
       const uint64_t a = replacement<true>(d, t, s, k, &v);
@@ -455,12 +462,17 @@ __global__ void __launch_bounds__(256) hbci_diag_kernel(const double* __restrict
 
 // Nonzeros of each row of H over V (replacements that land in V).
 __global__ void __launch_bounds__(64 * kWaves) hbci_count_kernel(const double* __restrict__ ints, int k, const Space V,
-                                                                 int64_t n, int32_t* __restrict__ cnt) {
+                                                                 int64_t n, int half, int32_t* __restrict__ cnt) {
   const Lds s = load_lds(ints, k);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint8_t* L = s.lists + wave * 64;
   for (int64_t a = (int64_t)blockIdx.x * kWaves + wave; a < n; a += (int64_t)gridDim.x * kWaves) {
-    const Det d = make_det(V.dets[a], k, L, lane);
+    const uint64_t key = V.dets[a];
+    if (half && !canonical(key)) {
+      if (lane == 0) cnt[a] = 0;
+      continue;
+    }
+    const Det d = make_det(key, k, L, lane);
     int c = 0;
     for (int t = lane; t < d.total; t += 64) {
       double v;
@@ -522,14 +534,16 @@ __global__ void scan_add_kernel(int64_t* __restrict__ ptr, int64_t n, const int6
 
 // Column indices and values of each row, in replacement order.
 __global__ void __launch_bounds__(64 * kWaves) hbci_fill_kernel(const double* __restrict__ ints, int k, const Space V,
-                                                                int64_t n, const int64_t* __restrict__ ptr,
+                                                                int64_t n, int half, const int64_t* __restrict__ ptr,
                                                                 int32_t* __restrict__ col, double* __restrict__ val) {
   const Lds s = load_lds(ints, k);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint8_t* L = s.lists + wave * 64;
   const uint64_t below = (1ull << lane) - 1ull;
   for (int64_t a = (int64_t)blockIdx.x * kWaves + wave; a < n; a += (int64_t)gridDim.x * kWaves) {
-    const Det d = make_det(V.dets[a], k, L, lane);
+    const uint64_t key = V.dets[a];
+    if (half && !canonical(key)) continue;
+    const Det d = make_det(key, k, L, lane);
     int64_t base = ptr[a];
     for (int t0 = 0; t0 < d.total; t0 += 64) {
       const int t = t0 + lane;
@@ -551,18 +565,26 @@ __global__ void __launch_bounds__(64 * kWaves) hbci_fill_kernel(const double* __
   }
 }
 
-// y = H x over V: the diagonal plus the CSR rows (one wave per row).
+// y = H x over V: the diagonal plus the CSR rows (one wave per row).  With
+// flip (flip-symmetric x, rows only for representatives) each row's value
+// is written to the row and to its partner.
 __global__ void __launch_bounds__(256) hbci_spmv_kernel(const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                                         const double* __restrict__ val, const double* __restrict__ diag,
-                                                        const double* __restrict__ x, double* __restrict__ y,
-                                                        int64_t n) {
+                                                        const uint64_t* __restrict__ dets,
+                                                        const int32_t* __restrict__ flip, const double* __restrict__ x,
+                                                        double* __restrict__ y, int64_t n) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
   for (int64_t a = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; a < n; a += nw) {
+    if (flip && !canonical(dets[a])) continue;
     double s = 0.0;
     for (int64_t e = ptr[a] + lane; e < ptr[a + 1]; e += 64) s += val[e] * x[col[e]];
     s = wave_sum(s);
-    if (lane == 0) y[a] = s + diag[a] * x[a];
+    if (lane == 0) {
+      const double ya = s + diag[a] * x[a];
+      y[a] = ya;
+      if (flip) y[flip[a]] = ya;
+    }
   }
 }
 
@@ -636,22 +658,41 @@ __global__ void hbci_scale_kernel(const double* __restrict__ in, double f, doubl
 }
 
 // N_a += H_ai c_i for every replacement a outside V with |H_ai c_i| > eps.
+// With half (flip-symmetric c, flip-closed V) only representatives i are
+// walked and N is kept for representatives b only: the term (i, b) of a
+// non-representative i equals (flip i, flip b), so a representative i adds
+// each term to its target's representative (twice for a flip-invariant
+// target, which i and flip(i) both reach); a flip-invariant i (a closed
+// shell, whose replacements come in flip pairs) adds only the terms whose
+// target is a representative.
 __global__ void __launch_bounds__(64 * kWaves) hbci_pt2_kernel(const double* __restrict__ ints, int k, const Space V,
                                                                const double* __restrict__ c, int64_t n, double eps,
-                                                               uint64_t* __restrict__ ek, double* __restrict__ ev,
-                                                               uint64_t emask, int64_t ecap) {
+                                                               int half, uint64_t* __restrict__ ek,
+                                                               double* __restrict__ ev, uint64_t emask, int64_t ecap) {
   const Lds s = load_lds(ints, k);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint8_t* L = s.lists + wave * 64;
   for (int64_t i = (int64_t)blockIdx.x * kWaves + wave; i < n; i += (int64_t)gridDim.x * kWaves) {
     const double ci = c[i];
-    if (ci == 0.0) continue;
-    const Det d = make_det(V.dets[i], k, L, lane);
+    const uint64_t key = V.dets[i];
+    if (ci == 0.0 || (half && !canonical(key))) continue;
+    const bool self = flip_key(key) == key;
+    const Det d = make_det(key, k, L, lane);
     for (int t = lane; t < d.total; t += 64) {
       double v;
-      const uint64_t a = replacement<true>(d, t, s, k, &v);
+      uint64_t a = replacement<true>(d, t, s, k, &v);
       const double hc = v * ci;
-      if (fabs(hc) > eps && ht_find(V.keys, V.vals, V.mask, a) < 0) ext_add(ek, ev, emask, ecap, a, hc, V.ctl);
+      if (!(fabs(hc) > eps)) continue;
+      double w = 1.0;
+      if (half) {
+        if (!canonical(a)) {
+          if (self) continue;
+          a = flip_key(a);
+        } else if (!self && flip_key(a) == a) {
+          w = 2.0;  // i and flip(i) reach the flip-invariant a with equal terms
+        }
+      }
+      if (ht_find(V.keys, V.vals, V.mask, a) < 0) ext_add(ek, ev, emask, ecap, a, w * hc, V.ctl);
     }
   }
 }
@@ -659,7 +700,7 @@ __global__ void __launch_bounds__(64 * kWaves) hbci_pt2_kernel(const double* __r
 // part[block] = partial sum of N_a^2 / (e - H_aa); part[kNB + block] = count
 __global__ void __launch_bounds__(256) hbci_e2_kernel(const double* __restrict__ ints, int k,
                                                       const uint64_t* __restrict__ ek, const double* __restrict__ ev,
-                                                      int64_t ecap, double e, double* __restrict__ part) {
+                                                      int64_t ecap, double e, int half, double* __restrict__ part) {
   const Lds s = load_lds(ints, k);
   double* red = (double*)s.lists;  // no static LDS beside the dynamic block
   double sum = 0.0, cnt = 0.0;
@@ -667,8 +708,10 @@ __global__ void __launch_bounds__(256) hbci_e2_kernel(const double* __restrict__
     const uint64_t key = ek[h];
     if (key == kEmpty) continue;
     const double na = ev[h];
-    sum += na * na / (e - diag_val(s, k, (uint32_t)key, (uint32_t)(key >> 32)));
-    cnt += 1.0;
+    // a representative stands for itself and its partner
+    const double w = (half && flip_key(key) != key) ? 2.0 : 1.0;
+    sum += w * (na * na / (e - diag_val(s, k, (uint32_t)key, (uint32_t)(key >> 32))));
+    cnt += w;
   }
   sum = group_sum(sum, red);
   if (threadIdx.x == 0) part[blockIdx.x] = sum;
@@ -793,6 +836,7 @@ struct Run {
   double* pin = nullptr;
   HbciCtl ctl{};
   int lds = 0;
+  int half = 0;  // flip-symmetric vectors over a flip-closed space: walk representatives only
 
   template <typename T>
   T* at(int64_t off) const {
@@ -862,7 +906,7 @@ struct Run {
   ifci_status build_h(int64_t n, hipError_t* he) {
     const int64_t nb = (n + 1023) / 1024;
     hipLaunchKernelGGL(hbci_count_kernel, dim3(blocks(n, kWaves, 8192)), dim3(64 * kWaves), lds, st,
-                       at<double>(L.ints), I.k, space(), n, at<int32_t>(L.cnt));
+                       at<double>(L.ints), I.k, space(), n, half, at<int32_t>(L.cnt));
     hipLaunchKernelGGL(scan_block_kernel, dim3((unsigned)nb), dim3(1024), 0, st, at<int32_t>(L.cnt), n,
                        at<int64_t>(L.ptr), at<int64_t>(L.bsum));
     hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, st, at<int64_t>(L.bsum), nb, at<HbciCtl>(L.ctl));
@@ -876,7 +920,7 @@ struct Run {
       return IFCI_ERR_OOM;
     }
     hipLaunchKernelGGL(hbci_fill_kernel, dim3(blocks(n, kWaves, 8192)), dim3(64 * kWaves), lds, st,
-                       at<double>(L.ints), I.k, space(), n, at<int64_t>(L.ptr), at<int32_t>(L.col),
+                       at<double>(L.ints), I.k, space(), n, half, at<int64_t>(L.ptr), at<int32_t>(L.col),
                        at<double>(L.val));
     *he = hipGetLastError();
     return *he == hipSuccess ? IFCI_OK : IFCI_ERR_DEVICE;
@@ -884,7 +928,8 @@ struct Run {
 
   hipError_t spmv(const double* x, double* y, int64_t n) {
     hipLaunchKernelGGL(hbci_spmv_kernel, dim3(blocks(n, 4, 8192)), dim3(256), 0, st, at<int64_t>(L.ptr),
-                       at<int32_t>(L.col), at<double>(L.val), at<double>(L.diag), x, y, n);
+                       at<int32_t>(L.col), at<double>(L.val), at<double>(L.diag), at<uint64_t>(L.dets),
+                       half ? at<int32_t>(L.flip) : nullptr, x, y, n);
     return hipGetLastError();
   }
 
@@ -976,10 +1021,10 @@ struct Run {
     hipLaunchKernelGGL(fill_f64_kernel, dim3(blocks((int64_t)L.ecap, 256, 4096)), dim3(256), 0, st, at<double>(L.ev),
                        (int64_t)L.ecap, 0.0);
     hipLaunchKernelGGL(hbci_pt2_kernel, dim3(blocks(n, kWaves, 8192)), dim3(64 * kWaves), lds, st,
-                       at<double>(L.ints), I.k, space(), c, n, eps2, at<uint64_t>(L.ek), at<double>(L.ev),
+                       at<double>(L.ints), I.k, space(), c, n, eps2, half, at<uint64_t>(L.ek), at<double>(L.ev),
                        L.ecap - 1, o.max_ext);
     hipLaunchKernelGGL(hbci_e2_kernel, dim3(kNB), dim3(256), lds, st, at<double>(L.ints), I.k, at<uint64_t>(L.ek),
-                       at<double>(L.ev), (int64_t)L.ecap, e_act, at<double>(L.part));
+                       at<double>(L.ev), (int64_t)L.ecap, e_act, half, at<double>(L.part));
     hipError_t e = hipGetLastError();
     double s[2];
     if (e == hipSuccess) e = read_parts(2, s);
@@ -1016,6 +1061,7 @@ int64_t hbci_work_bytes(int k, const ifci_hbci_options& o) { return layout(k, o)
 ifci_status hbci_solve(const HbciInc& I, const ifci_hbci_options& o, void* work, double* result, uint64_t* dets_out,
                        double* c_out, hipStream_t st) {
   Run R{I, o, layout(I.k, o), (char*)work, st};
+  R.half = 1;
   HB_TRY(R.prepare(), "hbci prepare");
   const double shift = R.ctl.e_core + I.e_const;
   HB_TRY(R.load(nullptr, 0), "hbci load");
@@ -1044,7 +1090,7 @@ ifci_status hbci_solve(const HbciInc& I, const ifci_hbci_options& o, void* work,
   while (steps < o.max_iter) {
     const int64_t n_old = n;
     hipLaunchKernelGGL(hbci_select_kernel, dim3(Run::blocks(n_old, kWaves, 8192)), dim3(64 * kWaves), R.lds, st,
-                       R.at<double>(R.L.ints), I.k, x, n_old, o.eps1, R.space());
+                       R.at<double>(R.L.ints), I.k, x, n_old, o.eps1, R.space(), R.half);
     HB_TRY(hipGetLastError(), "hbci select");
     HB_TRY(R.read_ctl(), "hbci select");
     ++steps;
@@ -1111,7 +1157,7 @@ ifci_status hbci_select(const HbciInc& I, const ifci_hbci_options& o, void* work
   HB_TRY(R.read_ctl(), "hbci load");
   if (R.ctl.flags) return capacity_failure(R.ctl.flags);
   hipLaunchKernelGGL(hbci_select_kernel, dim3(Run::blocks(n, kWaves, 8192)), dim3(64 * kWaves), R.lds, st,
-                     R.at<double>(R.L.ints), I.k, c, n, eps1, R.space());
+                     R.at<double>(R.L.ints), I.k, c, n, eps1, R.space(), 0);
   HB_TRY(hipGetLastError(), "hbci select");
   HB_TRY(R.read_ctl(), "hbci select");
   if (R.ctl.flags) return capacity_failure(R.ctl.flags);
