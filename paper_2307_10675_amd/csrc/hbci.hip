@@ -565,6 +565,129 @@ __global__ void __launch_bounds__(64 * kWaves) hbci_fill_kernel(const double* __
   }
 }
 
+// The rows of the determinants lo..n-1 added by a selection step, in a
+// space of representatives (flip-symmetric vectors): each such row is
+// counted from scratch, and each of its nonzeros (r, b) with b older than lo
+// also counts the entries it implies in the old rows, which H's symmetry and
+// its commuting with the flip fix: (b, r) when b is a representative, and
+// (flip b, flip r) when r is not flip-invariant and flip b is a
+// representative (for a flip-invariant r that entry is (flip b, r), reached
+// from r's own nonzero (r, flip b)).
+__global__ void __launch_bounds__(64 * kWaves) hbci_count_new_kernel(const double* __restrict__ ints, int k,
+                                                                     const Space V, int64_t lo, int64_t n,
+                                                                     const int32_t* __restrict__ flip,
+                                                                     int32_t* __restrict__ cnt,
+                                                                     int32_t* __restrict__ addc) {
+  const Lds s = load_lds(ints, k);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint8_t* L = s.lists + wave * 64;
+  for (int64_t r = lo + (int64_t)blockIdx.x * kWaves + wave; r < n; r += (int64_t)gridDim.x * kWaves) {
+    const uint64_t key = V.dets[r];
+    if (!canonical(key)) {
+      if (lane == 0) cnt[r] = 0;
+      continue;
+    }
+    const bool self = flip_key(key) == key;
+    const Det d = make_det(key, k, L, lane);
+    int c = 0;
+    for (int t = lane; t < d.total; t += 64) {
+      double v;
+      const int32_t j = ht_find(V.keys, V.vals, V.mask, replacement<false>(d, t, s, k, &v));
+      if (j < 0) continue;
+      ++c;
+      if (j < lo) {
+        const uint64_t kb = V.dets[j];
+        if (canonical(kb)) atomicAdd(addc + j, 1);
+        if (!self && canonical(flip_key(kb))) atomicAdd(addc + flip[j], 1);
+      }
+    }
+    c = wave_sum_int(c);
+    if (lane == 0) cnt[r] = c;
+  }
+}
+
+// cnt[a] = the old row's length plus its new entries, a < lo
+__global__ void hbci_rowlen_kernel(const int64_t* __restrict__ ptr_old, int64_t lo, const int32_t* __restrict__ addc,
+                                   int32_t* __restrict__ cnt) {
+  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < lo; a += (int64_t)gridDim.x * blockDim.x)
+    cnt[a] = (int32_t)(ptr_old[a + 1] - ptr_old[a]) + addc[a];
+}
+
+// The old rows' entries to the front of their new rows (one wave per row).
+__global__ void __launch_bounds__(256) hbci_copy_rows_kernel(const int64_t* __restrict__ ptr_old,
+                                                             const int32_t* __restrict__ col_old,
+                                                             const double* __restrict__ val_old, int64_t lo,
+                                                             const int64_t* __restrict__ ptr_new,
+                                                             int32_t* __restrict__ col_new,
+                                                             double* __restrict__ val_new) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t a = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; a < lo; a += nw) {
+    const int64_t b = ptr_old[a], len = ptr_old[a + 1] - b, to = ptr_new[a];
+    for (int64_t e = lane; e < len; e += 64) {
+      col_new[to + e] = col_old[b + e];
+      val_new[to + e] = val_old[b + e];
+    }
+  }
+}
+
+// The new rows in full (replacement order) and their implied entries in
+// the old rows, after the copied ones (in no fixed order).
+__global__ void __launch_bounds__(64 * kWaves) hbci_fill_new_kernel(const double* __restrict__ ints, int k,
+                                                                    const Space V, int64_t lo, int64_t n,
+                                                                    const int32_t* __restrict__ flip,
+                                                                    const int64_t* __restrict__ ptr_old,
+                                                                    const int64_t* __restrict__ ptr,
+                                                                    int32_t* __restrict__ pos, int32_t* __restrict__ col,
+                                                                    double* __restrict__ val) {
+  const Lds s = load_lds(ints, k);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint8_t* L = s.lists + wave * 64;
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (int64_t r = lo + (int64_t)blockIdx.x * kWaves + wave; r < n; r += (int64_t)gridDim.x * kWaves) {
+    const uint64_t key = V.dets[r];
+    if (!canonical(key)) continue;
+    const bool self = flip_key(key) == key;
+    const int32_t fr = flip[r];
+    const Det d = make_det(key, k, L, lane);
+    int64_t base = ptr[r];
+    for (int t0 = 0; t0 < d.total; t0 += 64) {
+      const int t = t0 + lane;
+      int32_t j = -1;
+      double v = 0.0;
+      if (t < d.total) {
+        j = ht_find(V.keys, V.vals, V.mask, replacement<false>(d, t, s, k, &v));
+        if (j >= 0) replacement<true>(d, t, s, k, &v);
+      }
+      const uint64_t m = __ballot(j >= 0);
+      if (j >= 0) {
+        const int64_t at = base + __popcll(m & below);
+        col[at] = j;
+        val[at] = v;
+        if (j < lo) {
+          const uint64_t kb = V.dets[j];
+          if (canonical(kb)) {
+            const int64_t e = ptr[j] + (ptr_old[j + 1] - ptr_old[j]) + atomicAdd(pos + j, 1);
+            col[e] = (int32_t)r;
+            val[e] = v;
+          }
+          if (!self && canonical(flip_key(kb))) {
+            const int32_t f = flip[j];
+            const int64_t e = ptr[f] + (ptr_old[f + 1] - ptr_old[f]) + atomicAdd(pos + f, 1);
+            col[e] = fr;
+            val[e] = v;
+          }
+        }
+      }
+      base += __popcll(m);
+    }
+  }
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
 // y = H x over V: the diagonal plus the CSR rows (one wave per row).  With
 // flip (flip-symmetric x, rows only for representatives) each row's value
 // is written to the row and to its partner.
@@ -730,7 +853,8 @@ uint64_t pow2_at_least(int64_t x) {
 }
 
 struct Layout {
-  int64_t ints, ctl, part, bsum, dets, keys, vals, flip, diag, cnt, ptr, col, val, basis, sig, x, w, r, t, ek, ev;
+  int64_t ints, ctl, part, bsum, dets, keys, vals, flip, diag, cnt, addc, pos, ptr[2], col[2], val[2], basis, sig, x, w,
+      r, t, ek, ev;
   int64_t bytes;
   uint64_t tcap, ecap;
 };
@@ -756,9 +880,14 @@ Layout layout(int k, const ifci_hbci_options& o) {
   L.flip = take(D * 4);
   L.diag = take(D * 8);
   L.cnt = take(D * 4);
-  L.ptr = take((D + 1) * 8);
-  L.col = take(o.max_nnz * 4);
-  L.val = take(o.max_nnz * 8);
+  L.addc = take(D * 4);
+  L.pos = take(D * 4);
+  // two CSR buffers: a selection step builds the new H from the old one
+  for (int b = 0; b < 2; ++b) {
+    L.ptr[b] = take((D + 1) * 8);
+    L.col[b] = take(o.max_nnz * 4);
+    L.val[b] = take(o.max_nnz * 8);
+  }
   L.basis = take((int64_t)o.m_max * D * 8);
   L.sig = take((int64_t)o.m_max * D * 8);
   L.x = take(D * 8);
@@ -837,6 +966,7 @@ struct Run {
   HbciCtl ctl{};
   int lds = 0;
   int half = 0;  // flip-symmetric vectors over a flip-closed space: walk representatives only
+  int cur = 0;   // the CSR buffer that holds H
 
   template <typename T>
   T* at(int64_t off) const {
@@ -877,6 +1007,7 @@ struct Run {
     hipError_t e = hipSuccess;
     for (const void* fn : {(const void*)hbci_select_kernel, (const void*)hbci_diag_kernel,
                            (const void*)hbci_count_kernel, (const void*)hbci_fill_kernel, (const void*)hbci_pt2_kernel,
+                           (const void*)hbci_count_new_kernel, (const void*)hbci_fill_new_kernel,
                            (const void*)hbci_e2_kernel})
       if (e == hipSuccess) e = allow_max_lds(fn);
     if (e != hipSuccess) return e;
@@ -904,13 +1035,24 @@ struct Run {
 
   // CSR of H over the n keys; IFCI_ERR_OOM past max_nnz
   ifci_status build_h(int64_t n, hipError_t* he) {
-    const int64_t nb = (n + 1023) / 1024;
     hipLaunchKernelGGL(hbci_count_kernel, dim3(blocks(n, kWaves, 8192)), dim3(64 * kWaves), lds, st,
                        at<double>(L.ints), I.k, space(), n, half, at<int32_t>(L.cnt));
+    ifci_status s = scan_rows(n, L.ptr[cur], he);
+    if (s != IFCI_OK) return s;
+    hipLaunchKernelGGL(hbci_fill_kernel, dim3(blocks(n, kWaves, 8192)), dim3(64 * kWaves), lds, st,
+                       at<double>(L.ints), I.k, space(), n, half, at<int64_t>(L.ptr[cur]), at<int32_t>(L.col[cur]),
+                       at<double>(L.val[cur]));
+    *he = hipGetLastError();
+    return *he == hipSuccess ? IFCI_OK : IFCI_ERR_DEVICE;
+  }
+
+  // row offsets at ptr_off from cnt[0..n); the total checked against max_nnz
+  ifci_status scan_rows(int64_t n, int64_t ptr_off, hipError_t* he) {
+    const int64_t nb = (n + 1023) / 1024;
     hipLaunchKernelGGL(scan_block_kernel, dim3((unsigned)nb), dim3(1024), 0, st, at<int32_t>(L.cnt), n,
-                       at<int64_t>(L.ptr), at<int64_t>(L.bsum));
+                       at<int64_t>(ptr_off), at<int64_t>(L.bsum));
     hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, st, at<int64_t>(L.bsum), nb, at<HbciCtl>(L.ctl));
-    hipLaunchKernelGGL(scan_add_kernel, dim3(blocks(n, 256, 1 << 30)), dim3(256), 0, st, at<int64_t>(L.ptr), n,
+    hipLaunchKernelGGL(scan_add_kernel, dim3(blocks(n, 256, 1 << 30)), dim3(256), 0, st, at<int64_t>(ptr_off), n,
                        at<int64_t>(L.bsum));
     *he = hipGetLastError();
     if (*he == hipSuccess) *he = read_ctl();
@@ -919,16 +1061,39 @@ struct Run {
       set_error("HBCI: H over the selected space has more nonzeros than max_nnz");
       return IFCI_ERR_OOM;
     }
-    hipLaunchKernelGGL(hbci_fill_kernel, dim3(blocks(n, kWaves, 8192)), dim3(64 * kWaves), lds, st,
-                       at<double>(L.ints), I.k, space(), n, half, at<int64_t>(L.ptr), at<int32_t>(L.col),
-                       at<double>(L.val));
+    return IFCI_OK;
+  }
+
+  // H over n keys from H over the first lo (representative rows, flip
+  // partners known): the new rows from scratch, the old ones copied and
+  // extended by the entries the new rows imply; the result in the other
+  // buffer, which becomes current.
+  ifci_status extend_h(int64_t lo, int64_t n, hipError_t* he) {
+    const int nxt = cur ^ 1;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(blocks(lo, 256, 4096)), dim3(256), 0, st, at<int32_t>(L.addc), lo, 0);
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(blocks(lo, 256, 4096)), dim3(256), 0, st, at<int32_t>(L.pos), lo, 0);
+    hipLaunchKernelGGL(hbci_count_new_kernel, dim3(blocks(n - lo, kWaves, 8192)), dim3(64 * kWaves), lds, st,
+                       at<double>(L.ints), I.k, space(), lo, n, at<int32_t>(L.flip), at<int32_t>(L.cnt),
+                       at<int32_t>(L.addc));
+    hipLaunchKernelGGL(hbci_rowlen_kernel, dim3(blocks(lo, 256, 4096)), dim3(256), 0, st, at<int64_t>(L.ptr[cur]), lo,
+                       at<int32_t>(L.addc), at<int32_t>(L.cnt));
+    ifci_status s = scan_rows(n, L.ptr[nxt], he);
+    if (s != IFCI_OK) return s;
+    hipLaunchKernelGGL(hbci_copy_rows_kernel, dim3(blocks(lo, 4, 8192)), dim3(256), 0, st, at<int64_t>(L.ptr[cur]),
+                       at<int32_t>(L.col[cur]), at<double>(L.val[cur]), lo, at<int64_t>(L.ptr[nxt]),
+                       at<int32_t>(L.col[nxt]), at<double>(L.val[nxt]));
+    hipLaunchKernelGGL(hbci_fill_new_kernel, dim3(blocks(n - lo, kWaves, 8192)), dim3(64 * kWaves), lds, st,
+                       at<double>(L.ints), I.k, space(), lo, n, at<int32_t>(L.flip), at<int64_t>(L.ptr[cur]),
+                       at<int64_t>(L.ptr[nxt]), at<int32_t>(L.pos), at<int32_t>(L.col[nxt]), at<double>(L.val[nxt]));
     *he = hipGetLastError();
-    return *he == hipSuccess ? IFCI_OK : IFCI_ERR_DEVICE;
+    if (*he != hipSuccess) return IFCI_ERR_DEVICE;
+    cur = nxt;
+    return IFCI_OK;
   }
 
   hipError_t spmv(const double* x, double* y, int64_t n) {
-    hipLaunchKernelGGL(hbci_spmv_kernel, dim3(blocks(n, 4, 8192)), dim3(256), 0, st, at<int64_t>(L.ptr),
-                       at<int32_t>(L.col), at<double>(L.val), at<double>(L.diag), at<uint64_t>(L.dets),
+    hipLaunchKernelGGL(hbci_spmv_kernel, dim3(blocks(n, 4, 8192)), dim3(256), 0, st, at<int64_t>(L.ptr[cur]),
+                       at<int32_t>(L.col[cur]), at<double>(L.val[cur]), at<double>(L.diag), at<uint64_t>(L.dets),
                        half ? at<int32_t>(L.flip) : nullptr, x, y, n);
     return hipGetLastError();
   }
@@ -1105,7 +1270,7 @@ ifci_status hbci_solve(const HbciInc& I, const ifci_hbci_options& o, void* work,
                        n - n_old, 0.0);
     HB_TRY(hipGetLastError(), "hbci start");
     hipError_t he;
-    ifci_status s = R.build_h(n, &he);
+    ifci_status s = R.extend_h(n_old, n, &he);
     if (s == IFCI_ERR_DEVICE) return device_failure(he, "hbci H");
     if (s != IFCI_OK) return s;
     bool cv;
