@@ -62,13 +62,15 @@ def dump_gradient(name, problem, jobs, n_sample=4096, seed=3):
     1- and 2-particle densities) from the oracle, in increment order: the
     whole dE/dh and a seeded sample of dE/d(pq|rs) entries (with the
     Frobenius norm of the whole array), as JSON."""
-    t = time.time()
+    t = t0 = time.time()
     subsets = ifci.increments(problem.n_bodies, problem.order)
     E, gap = {}, {}
 
     def stream(ex):
-        for S, d in ex.map(_densities, [(problem, S) for S in subsets], chunksize=1):
+        for t, (S, d) in enumerate(ex.map(_densities, [(problem, S) for S in subsets], chunksize=1)):
             E[S], gap[S] = d["E"], d["gap"]
+            if (t + 1) % 50 == 0:
+                print(f"{name}: {t + 1} of {len(subsets)} increments, {time.time() - t0:.0f} s", flush=True)
             yield S, d
 
     with ProcessPoolExecutor(max_workers=jobs) as ex:
