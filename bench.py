@@ -23,7 +23,8 @@ Legs (--legs, comma separated; default all):
   w4     256 independent 10o10e problems (K = 20, seeds 4000..4255)
   cnb    connected n-body screening at 10^-4.6 Eh on a decaying 10-body chain
   sno    summation natural orbitals: 6 occupied + 12 virtuals, order 3
-  hbci   heat-bath selected CI + EN-PT2 on a 16o16e increment against its FCI
+  hbci   heat-bath selected CI + EN-PT2 on a 16o16e increment against its FCI,
+         and whole HBCI expansions of workloads 1 and 2
   cpu    the oracle on the host cores
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs mixed,fp64,...]
@@ -444,8 +445,42 @@ def hbci_leg(torch, ifci, synthetic):
         del work
         torch.cuda.empty_cache()
     pl.close()
+    # whole expansions with HBCI as the increment solver (eps1 = 1 mEh,
+    # eps2 = 1 uEh), increments overlapped by host workers, against the
+    # exact expansion's total from the stored oracle energies
+    expansions = []
+    for wl in (1, 2):
+        prob = synthetic.workload(wl)
+        path = os.path.join(ROOT, "tests", "golden", f"oracle_w{wl}.json")
+        exact = e_inc = None
+        if os.path.exists(path):
+            with open(path) as f:
+                gdoc = json.load(f)
+            if gdoc.get("sha256") == prob.sha256():
+                exact = gdoc["total"]
+                e_inc = np.array([x["E"] for x in gdoc["increments"]])
+        plx = ifci.Plan(prob, tuning=None).attach(prob.h, prob.eri)
+        opts = ifci.hbci_options(eps1=1e-3, eps2=1e-6, max_det=1 << 13, max_nnz=1 << 22, max_ext=1 << 18,
+                                 r_tol=1e-6)
+        row = dict(workload=wl, increments=plx.n_inc)
+        for workers in (1, 8):
+            out = plx.hbci_expansion(opts, workers=workers)
+            row[f"seconds_{workers}_workers"] = round(out["seconds"], 4)
+        row["increments_per_s_8_workers"] = plx.n_inc / row["seconds_8_workers"]
+        row["all_converged"] = all(r["converged"] for r in out["results"])
+        row["total"] = out["energy"]["total"]
+        if exact is not None:
+            row["total_minus_exact_Eh"] = out["energy"]["total"] - exact
+            # increments whose HBCI energy is more than 1 mEh from the exact
+            # one (a selected space grown from the reference cannot reach a
+            # ground state that has almost no weight on it)
+            d = np.array([r["E"] for r in out["results"]]) - e_inc
+            row["increments_off_by_1mEh"] = int((np.abs(d) > 1e-3).sum())
+            row["max_increment_error_Eh"] = float(np.abs(d).max())
+        plx.close()
+        expansions.append(row)
     return dict(increment="16o16e (merged 8-body chain, seed 4108)", fci_seconds_mixed=round(fci_s, 3),
-                E_fci=e_fci, runs=runs)
+                E_fci=e_fci, runs=runs, expansions=expansions)
 
 
 def main():

@@ -450,6 +450,18 @@ ifci_status ifci_hbci_solve(ifci_plan_t plan, int64_t inc, const ifci_hbci_optio
                             int64_t work_bytes, double* result, uint64_t* dets_out, double* c_out,
                             ifci_stream_t stream);
 
+/* ifci_hbci_solve of increments first .. first+count-1 by n_workers host
+ * threads (1..64), each with a stream of its own (created and destroyed
+ * here) and its own work buffer works[w] (host array of n_workers device
+ * pointers, each work_bytes long and at least ifci_hbci_work_bytes of every
+ * increment of the range); the largest increments start first.  results:
+ * host [count][8], each row as ifci_hbci_solve's result.  Returns when every
+ * increment is done; the first failure stops the workers and is returned
+ * (the other rows are then undefined).  The increments are independent, so
+ * their small host-driven loops overlap on the device. */
+ifci_status ifci_hbci_solve_range(ifci_plan_t plan, int64_t first, int64_t count, const ifci_hbci_options* options,
+                                  void* const* works, int64_t work_bytes, int32_t n_workers, double* results);
+
 /* The steps of ifci_hbci_solve on a caller's space, for checking them.
  * dets: device [n] distinct keys (n <= max_det); c: device [n].
  * ifci_hbci_sigma: sigma (device [n]) = (H - E_core - e_const) c over the

@@ -1227,6 +1227,64 @@ ifci_status ifci_hbci_solve(ifci_plan_t p, int64_t inc, const ifci_hbci_options*
   return hbci_solve(I, *o, work, result, dets_out, c_out, (hipStream_t)stream);
 }
 
+ifci_status ifci_hbci_solve_range(ifci_plan_t p, int64_t first, int64_t count, const ifci_hbci_options* o,
+                                  void* const* works, int64_t work_bytes, int32_t n_workers, double* results) {
+  if (check_plan(p) != IFCI_OK) return IFCI_ERR_ARG;
+  if (first < 0 || count < 0 || first + count > (int64_t)p->inc.size() || !o || !works || !results ||
+      n_workers < 1 || n_workers > 64) {
+    set_error("ifci_hbci_solve_range: bad range, null pointer or n_workers outside 1..64");
+    return IFCI_ERR_ARG;
+  }
+  for (int w = 0; w < n_workers; ++w) {
+    HbciInc I;
+    for (int64_t i = first; i < first + count; ++i) {
+      ifci_status s = hbci_setup(p, i, o, works[w], work_bytes, &I);
+      if (s != IFCI_OK) return s;
+    }
+  }
+  if (count == 0) return IFCI_OK;
+  // largest first, so that the last increments to start are short
+  std::vector<int64_t> order(count);
+  for (int64_t j = 0; j < count; ++j) order[j] = first + j;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int64_t a, int64_t b) { return p->inc[a].n_det > p->inc[b].n_det; });
+  std::atomic<int64_t> next(0);
+  std::mutex mu;
+  ifci_status first_status = IFCI_OK;
+  std::string first_msg;
+  std::vector<std::thread> pool;
+  pool.reserve(n_workers);
+  for (int w = 0; w < n_workers; ++w)
+    pool.emplace_back([&, w] {
+      ifci_status s = IFCI_OK;
+      hipStream_t st = nullptr;
+      if (hipSetDevice(p->device) != hipSuccess || hipStreamCreate(&st) != hipSuccess) {
+        set_error("ifci_hbci_solve_range: no stream for a worker");
+        s = IFCI_ERR_DEVICE;
+      }
+      while (s == IFCI_OK) {
+        const int64_t j = next.fetch_add(1);
+        if (j >= count) break;
+        const int64_t i = order[j];
+        HbciInc I;
+        s = hbci_setup(p, i, o, works[w], work_bytes, &I);
+        if (s == IFCI_OK) s = hbci_solve(I, *o, works[w], results + (i - first) * 8, nullptr, nullptr, st);
+      }
+      if (st) (void)hipStreamDestroy(st);
+      if (s != IFCI_OK) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (first_status == IFCI_OK) {
+          first_status = s;
+          first_msg = ifci_last_error();
+        }
+        next.store(count);
+      }
+    });
+  for (std::thread& t : pool) t.join();
+  if (first_status != IFCI_OK) set_error(first_msg);
+  return first_status;
+}
+
 ifci_status ifci_hbci_sigma(ifci_plan_t p, int64_t inc, const ifci_hbci_options* o, void* work, int64_t work_bytes,
                             const uint64_t* dets, int64_t n, const double* c, double* sigma, ifci_stream_t stream) {
   HbciInc I;

@@ -43,6 +43,7 @@ constexpr int kNB = 512;        // workgroups of the vector kernels
 constexpr int kWaves = 4;       // waves per workgroup of the per-determinant kernels
 constexpr int kMaxM = 16;       // largest Davidson subspace
 constexpr int kParts = kMaxM + 1;
+constexpr int kKeepRitz = 4;    // Ritz vectors kept at a Davidson restart
 
 enum : unsigned { kFlagDetCap = 1u, kFlagExtCap = 2u, kFlagDuplicate = 4u, kFlagNoPartner = 8u };
 
@@ -57,6 +58,10 @@ struct HbciCtl {
 
 struct Coef {
   double v[kMaxM];
+};
+
+struct CoefKeep {
+  double v[kMaxM][kKeepRitz];
 };
 
 __device__ __forceinline__ uint64_t hmix(uint64_t x) {
@@ -780,6 +785,20 @@ __global__ void hbci_scale_kernel(const double* __restrict__ in, double f, doubl
     out[i] = f * in[i];
 }
 
+// out_j = sum_l Y[l][j] B_l, j < keep (the kept Ritz vectors of a restart)
+__global__ void __launch_bounds__(256) hbci_combo_kernel(const double* __restrict__ B, int64_t ld, int m, CoefKeep Y,
+                                                         int keep, double* __restrict__ out, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double b[kMaxM];
+    for (int l = 0; l < m; ++l) b[l] = B[l * ld + i];
+    for (int j = 0; j < keep; ++j) {
+      double a = 0.0;
+      for (int l = 0; l < m; ++l) a += Y.v[l][j] * b[l];
+      out[j * ld + i] = a;
+    }
+  }
+}
+
 // N_a += H_ai c_i for every replacement a outside V with |H_ai c_i| > eps.
 // With half (flip-symmetric c, flip-closed V) only representatives i are
 // walked and N is kept for representatives b only: the term (i, b) of a
@@ -854,7 +873,7 @@ uint64_t pow2_at_least(int64_t x) {
 
 struct Layout {
   int64_t ints, ctl, part, bsum, dets, keys, vals, flip, diag, cnt, addc, pos, ptr[2], col[2], val[2], basis, sig, x, w,
-      r, t, ek, ev;
+      r, t, keep, ek, ev;
   int64_t bytes;
   uint64_t tcap, ecap;
 };
@@ -894,14 +913,16 @@ Layout layout(int k, const ifci_hbci_options& o) {
   L.w = take(D * 8);
   L.r = take(D * 8);
   L.t = take(D * 8);
+  L.keep = take((int64_t)2 * kKeepRitz * D * 8);
   L.ek = take((int64_t)L.ecap * 8);
   L.ev = take((int64_t)L.ecap * 8);
   L.bytes = off;
   return L;
 }
 
-// Lowest eigenpair of the symmetric m x m matrix A (cyclic Jacobi).
-void lowest_eigen(const double (&A0)[kMaxM][kMaxM], int m, double* theta, double* y) {
+// Eigenpairs of the symmetric m x m matrix A (cyclic Jacobi), ascending:
+// evals[j] with the unit eigenvector in column j of Y.
+void sym_eigen(const double (&A0)[kMaxM][kMaxM], int m, double* evals, double (&Y)[kMaxM][kMaxM]) {
   double A[kMaxM][kMaxM], Q[kMaxM][kMaxM];
   for (int i = 0; i < m; ++i)
     for (int j = 0; j < m; ++j) {
@@ -939,14 +960,25 @@ void lowest_eigen(const double (&A0)[kMaxM][kMaxM], int m, double* theta, double
         }
       }
   }
-  int lo = 0;
-  for (int i = 1; i < m; ++i)
-    if (A[i][i] < A[lo][lo]) lo = i;
-  *theta = A[lo][lo];
-  double nrm = 0.0;
-  for (int i = 0; i < m; ++i) nrm += Q[i][lo] * Q[i][lo];
-  nrm = std::sqrt(nrm);
-  for (int i = 0; i < m; ++i) y[i] = Q[i][lo] / nrm;
+  int idx[kMaxM];
+  for (int i = 0; i < m; ++i) idx[i] = i;
+  for (int i = 1; i < m; ++i)  // insertion sort by eigenvalue
+    for (int j = i; j > 0 && A[idx[j]][idx[j]] < A[idx[j - 1]][idx[j - 1]]; --j) std::swap(idx[j], idx[j - 1]);
+  for (int j = 0; j < m; ++j) {
+    const int c = idx[j];
+    evals[j] = A[c][c];
+    double nrm = 0.0;
+    for (int i = 0; i < m; ++i) nrm += Q[i][c] * Q[i][c];
+    nrm = std::sqrt(nrm);
+    for (int i = 0; i < m; ++i) Y[i][j] = Q[i][c] / nrm;
+  }
+}
+
+void lowest_eigen(const double (&A)[kMaxM][kMaxM], int m, double* theta, double* y) {
+  double ev[kMaxM], Y[kMaxM][kMaxM];
+  sym_eigen(A, m, ev, Y);
+  *theta = ev[0];
+  for (int i = 0; i < m; ++i) y[i] = Y[i][0];
 }
 
 // Pinned host staging for read-backs, one per host thread.
@@ -1138,24 +1170,37 @@ struct Run {
         *conv = true;
         break;
       }
-      if (m == o.m_max) {  // restart from the Ritz vector
-        hipLaunchKernelGGL(hbci_scale_kernel, dim3(gb), dim3(256), 0, st, x, 1.0, Vb, n);
-        hipLaunchKernelGGL(hbci_scale_kernel, dim3(gb), dim3(256), 0, st, w, 1.0, Sb, n);
+      if (m == o.m_max) {  // thick restart: the lowest Ritz vectors and their sigmas
+        const int keep = std::min(kKeepRitz, o.m_max / 2);
+        double ev[kMaxM], Y[kMaxM][kMaxM];
+        sym_eigen(Hs, m, ev, Y);
+        CoefKeep K{};
+        for (int l = 0; l < m; ++l)
+          for (int j = 0; j < keep; ++j) K.v[l][j] = Y[l][j];
+        double* kv = at<double>(L.keep);
+        double* ks = kv + (int64_t)kKeepRitz * ld;
+        hipLaunchKernelGGL(hbci_combo_kernel, dim3(gb), dim3(256), 0, st, Vb, ld, m, K, keep, kv, n);
+        hipLaunchKernelGGL(hbci_combo_kernel, dim3(gb), dim3(256), 0, st, Sb, ld, m, K, keep, ks, n);
+        for (int j = 0; j < keep; ++j) {
+          hipLaunchKernelGGL(hbci_scale_kernel, dim3(gb), dim3(256), 0, st, kv + j * ld, 1.0, Vb + j * ld, n);
+          hipLaunchKernelGGL(hbci_scale_kernel, dim3(gb), dim3(256), 0, st, ks + j * ld, 1.0, Sb + j * ld, n);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
         for (int i = 0; i < kMaxM; ++i)
           for (int j = 0; j < kMaxM; ++j) Hs[i][j] = 0.0;
-        Hs[0][0] = theta;
-        m = 1;
+        for (int j = 0; j < keep; ++j) Hs[j][j] = ev[j];
+        m = keep;
       }
       hipLaunchKernelGGL(hbci_precond_kernel, dim3(gb), dim3(256), 0, st, r, at<double>(L.diag),
                          at<int32_t>(L.flip), theta, t, n);
       double t2 = 0.0;
-      for (int pass = 0; pass < 2; ++pass) {
+      for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
         Coef d{};
         if ((e = dots(Vb, m, t, n, d.v)) != hipSuccess) return e;
         hipLaunchKernelGGL(hbci_orth_kernel, dim3(kNB), dim3(256), 0, st, Vb, ld, m, d, t, n, at<double>(L.part));
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((e = read_parts(1, &t2)) != hipSuccess) return e;
       }
+      if ((e = read_parts(1, &t2)) != hipSuccess) return e;
       if (!(t2 > 1e-28)) break;  // the space is exhausted
       hipLaunchKernelGGL(hbci_scale_kernel, dim3(gb), dim3(256), 0, st, t, 1.0 / std::sqrt(t2), Vb + m * ld, n);
       if ((e = spmv(Vb + m * ld, Sb + m * ld, n)) != hipSuccess) return e;

@@ -101,6 +101,9 @@ _SIGNATURES = {
     "ifci_hbci_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(HbciOptions),
                                        ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "ifci_hbci_solve_range": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                             ctypes.POINTER(HbciOptions), ctypes.POINTER(ctypes.c_void_p),
+                                             ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "ifci_hbci_sigma": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(HbciOptions),
                                        ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -462,26 +465,36 @@ class Plan:
                                    _ptr(c), e_var, eps2, ctypes.byref(e2), ctypes.byref(n), _stream(stream)))
         return e2.value, n.value
 
-    def hbci_expansion(self, opts: HbciOptions | None = None, stream=None):
-        """Every increment by HBCI (E = E_var + E_PT2), then the energy sums
-        of eqs. 1-5: dict(results, energy, seconds)."""
+    def hbci_expansion(self, opts: HbciOptions | None = None, workers: int = 8, stream=None):
+        """Every increment by HBCI (E = E_var + E_PT2; ifci_hbci_solve_range
+        with `workers` host threads), then the energy sums of eqs. 1-5:
+        dict(results, energy, seconds)."""
         import time
 
         import torch
         opts = opts or hbci_options()
         dev = torch.device("cuda", self.device)
+        n = self.n_inc
+        nb = 0
+        for i in range(n):
+            b = ctypes.c_int64()
+            _check(lib().ifci_hbci_work_bytes(self._h, i, ctypes.byref(opts), ctypes.byref(b)))
+            nb = max(nb, b.value)
+        bufs = [torch.empty(nb // 8 + 64, dtype=torch.float64, device=dev) for _ in range(workers)]
+        ptrs = (ctypes.c_void_p * workers)(*[b.data_ptr() + (-b.data_ptr()) % 256 for b in bufs])
+        res = (ctypes.c_double * (8 * n))()
+        torch.cuda.synchronize(dev)
         t0 = time.perf_counter()
-        by_k, results = {}, []
-        for i in range(self.n_inc):
-            k = self.increment(i).n_act
-            if k not in by_k:
-                by_k[k] = self.hbci_work(i, opts)
-            results.append(self.hbci(i, opts, work=by_k[k], stream=stream))
+        _check(lib().ifci_hbci_solve_range(self._h, 0, n, ctypes.byref(opts), ptrs, nb, workers, res))
+        secs = time.perf_counter() - t0
+        results = [dict(E_var=res[8 * i], E_pt2=res[8 * i + 1], E=res[8 * i] + res[8 * i + 1],
+                        n_det=int(res[8 * i + 2]), n_iter=int(res[8 * i + 3]), converged=bool(res[8 * i + 4]),
+                        residual=res[8 * i + 5], n_ext=int(res[8 * i + 6]), nnz=int(res[8 * i + 7]))
+                   for i in range(n)]
         E = torch.tensor([r["E"] for r in results], dtype=torch.float64, device=dev)
         st = torch.tensor([1 if r["converged"] else 2 for r in results], dtype=torch.int32, device=dev)
         en = self.energy(E, st, stream=stream)
-        return dict(results=results, energy=en, seconds=time.perf_counter() - t0)
-
+        return dict(results=results, energy=en, seconds=secs)
 
 def davidson_group(plans, stream=None):
     """ifci_davidson_group over attached plans: one batched solve of every
