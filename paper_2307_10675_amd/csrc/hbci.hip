@@ -40,7 +40,10 @@ namespace {
 
 constexpr uint64_t kEmpty = ~0ull;
 constexpr int kNB = 512;        // workgroups of the vector kernels
-constexpr int kWaves = 4;       // waves per workgroup of the per-determinant kernels
+// Waves per workgroup of the kernels that hold the integrals in LDS: at 16
+// orbitals (77 KB) two workgroups fit a CU, so 16 waves each keep 32 waves
+// of table probes in flight per CU.
+constexpr int kWaves = 16;
 constexpr int kMaxM = 16;       // largest Davidson subspace
 constexpr int kParts = kMaxM + 1;
 constexpr int kKeepRitz = 4;    // Ritz vectors kept at a Davidson restart
@@ -450,7 +453,7 @@ __global__ void __launch_bounds__(64 * kWaves) hbci_select_kernel(const double* 
 }
 
 // The diagonal (and, with partners, each key's flip partner) of rows lo..n-1.
-__global__ void __launch_bounds__(256) hbci_diag_kernel(const double* __restrict__ ints, int k, const Space V,
+__global__ void __launch_bounds__(64 * kWaves) hbci_diag_kernel(const double* __restrict__ ints, int k, const Space V,
                                                         int64_t lo, int64_t n, int partners, double* __restrict__ diag,
                                                         int32_t* __restrict__ flip) {
   const Lds s = load_lds(ints, k);
@@ -840,7 +843,7 @@ __global__ void __launch_bounds__(64 * kWaves) hbci_pt2_kernel(const double* __r
 }
 
 // part[block] = partial sum of N_a^2 / (e - H_aa); part[kNB + block] = count
-__global__ void __launch_bounds__(256) hbci_e2_kernel(const double* __restrict__ ints, int k,
+__global__ void __launch_bounds__(64 * kWaves) hbci_e2_kernel(const double* __restrict__ ints, int k,
                                                       const uint64_t* __restrict__ ek, const double* __restrict__ ev,
                                                       int64_t ecap, double e, int half, double* __restrict__ part) {
   const Lds s = load_lds(ints, k);
@@ -1060,7 +1063,7 @@ struct Run {
 
   hipError_t diag(int64_t lo, int64_t n, bool partners) {
     if (n <= lo) return hipSuccess;
-    hipLaunchKernelGGL(hbci_diag_kernel, dim3(blocks(n - lo, 256, 2048)), dim3(256), lds, st, at<double>(L.ints), I.k,
+    hipLaunchKernelGGL(hbci_diag_kernel, dim3(blocks(n - lo, 64 * kWaves, 2048)), dim3(64 * kWaves), lds, st, at<double>(L.ints), I.k,
                        space(), lo, n, partners ? 1 : 0, at<double>(L.diag), at<int32_t>(L.flip));
     return hipGetLastError();
   }
@@ -1233,7 +1236,7 @@ struct Run {
     hipLaunchKernelGGL(hbci_pt2_kernel, dim3(blocks(n, kWaves, 8192)), dim3(64 * kWaves), lds, st,
                        at<double>(L.ints), I.k, space(), c, n, eps2, half, at<uint64_t>(L.ek), at<double>(L.ev),
                        L.ecap - 1, o.max_ext);
-    hipLaunchKernelGGL(hbci_e2_kernel, dim3(kNB), dim3(256), lds, st, at<double>(L.ints), I.k, at<uint64_t>(L.ek),
+    hipLaunchKernelGGL(hbci_e2_kernel, dim3(kNB), dim3(64 * kWaves), lds, st, at<double>(L.ints), I.k, at<uint64_t>(L.ek),
                        at<double>(L.ev), (int64_t)L.ecap, e_act, half, at<double>(L.part));
     hipError_t e = hipGetLastError();
     double s[2];
