@@ -18,7 +18,10 @@ pytestmark = pytest.mark.gpu
 C = 10 ** -4.6  # the paper's screening parameter (Eh)
 
 
-@pytest.mark.parametrize("precision,r_tol,tol", [(ifci.FP64, 1e-8, 1e-9), (ifci.MIXED, 1e-5, 1e-6)])
+# mixed precision refined to an FP64 residual of 1e-7: the closest pair
+# increment of this chain lies 3.8e-6 Eh from C, so the energies must be
+# good to far better than that for both sides to take the same decisions
+@pytest.mark.parametrize("precision,r_tol,tol", [(ifci.FP64, 1e-8, 1e-9), (ifci.MIXED, 1e-7, 1e-8)])
 def test_screened_expansion_against_oracle(precision, r_tol, tol):
     p = synthetic.local_chain(10, seed=5100, order=4, rate=1.0)
     g = load_golden("local10")
