@@ -59,7 +59,7 @@ def _invariants(p, r, tol):
     assert abs(e_euler - r["total"]) <= tol * max(1.0, abs(r["total"]))
 
 
-def _finite_differences(p, r, n_h, n_eri, seed, opts, tol):
+def _finite_differences(p, r, n_h, n_eri, seed, opts, tol, richardson=False):
     rng = np.random.default_rng(seed)
     n = p.n_orb
 
@@ -69,23 +69,38 @@ def _finite_differences(p, r, n_h, n_eri, seed, opts, tol):
         assert (res["status"].cpu().numpy() == ifci.INC_DONE).all()
         return res["total"]
 
+    def central(f, step):
+        return (f(step) - f(-step)) / (2 * step)
+
+    def derivative(f):
+        # central differences at steps d and 2d, Richardson-extrapolated:
+        # the step^2 term (large where an increment is nearly degenerate)
+        # cancels, leaving step^4
+        return (4 * central(f, STEP) - central(f, 2 * STEP)) / 3 if richardson else central(f, STEP)
+
     for _ in range(n_h):
         a, b = sorted(int(v) for v in rng.choice(n, 2, replace=True))
-        hp, hm = p.h.copy(), p.h.copy()
-        for (x, y) in {(a, b), (b, a)}:
-            hp[x, y] += STEP
-            hm[x, y] -= STEP
-        fd = (energy(hp, p.eri) - energy(hm, p.eri)) / (2 * STEP)
+
+        def f_h(d):
+            hd = p.h.copy()
+            for (x, y) in {(a, b), (b, a)}:
+                hd[x, y] += d
+            return energy(hd, p.eri)
+
+        fd = derivative(f_h)
         an = sum(r["dh"][x, y] for (x, y) in {(a, b), (b, a)})
         assert abs(fd - an) <= tol * max(1.0, abs(an)), ("h", a, b, fd, an)
     for _ in range(n_eri):
         idx = tuple(int(v) for v in rng.choice(n, 4, replace=True))
         orb = _orbit(*idx)
-        gp, gm = p.eri.copy(), p.eri.copy()
-        for t in orb:
-            gp[t] += STEP
-            gm[t] -= STEP
-        fd = (energy(p.h, gp) - energy(p.h, gm)) / (2 * STEP)
+
+        def f_g(d):
+            gd = p.eri.copy()
+            for t in orb:
+                gd[t] += d
+            return energy(p.h, gd)
+
+        fd = derivative(f_g)
         an = sum(r["dg"][t] for t in orb)
         assert abs(fd - an) <= tol * max(1.0, abs(an)), ("eri", idx, fd, an)
 
@@ -135,11 +150,12 @@ def test_order4_gradient_against_oracle(order4):
 
 
 def test_order4_finite_differences(order4):
-    """Central differences (step 1e-5) of the FP64 GPU energy on 16 seeded
-    h pairs and 16 seeded eri orbits against the GPU adjoint."""
+    """Central differences (steps 1e-5 and 2e-5, Richardson-extrapolated) of
+    the FP64 GPU energy on 16 seeded h pairs and 16 seeded eri orbits
+    against the GPU adjoint."""
     p, g, r64, r32 = order4
     print("[w3] order 4 finite differences", flush=True)
-    _finite_differences(p, r64, 16, 16, 3001, dict(r_tol=1e-10, max_iter=600), 1e-7)
+    _finite_differences(p, r64, 16, 16, 3001, dict(r_tol=1e-10, max_iter=600), 1e-7, richardson=True)
 
 
 def test_order5_invariants_mixed_and_finite_differences():
