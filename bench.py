@@ -468,10 +468,10 @@ def hbci_leg(torch, ifci, synthetic, increment_only=False):
         opts = ifci.hbci_options(eps1=1e-3, eps2=1e-6, max_det=1 << 13, max_nnz=1 << 22, max_ext=1 << 18,
                                  r_tol=1e-6)
         row = dict(workload=wl, increments=plx.n_inc)
-        for workers in ((1, 8) if wl == 1 else (8,)):
+        for workers in ((1, 16) if wl == 1 else (16,)):
             out = plx.hbci_expansion(opts, workers=workers)
             row[f"seconds_{workers}_workers"] = round(out["seconds"], 4)
-        row["increments_per_s_8_workers"] = plx.n_inc / row["seconds_8_workers"]
+        row["increments_per_s_16_workers"] = plx.n_inc / row["seconds_16_workers"]
         row["all_converged"] = all(r["converged"] for r in out["results"])
         row["total"] = out["energy"]["total"]
         if exact is not None:

@@ -864,6 +864,213 @@ __global__ void __launch_bounds__(64 * kWaves) hbci_e2_kernel(const double* __re
   if (threadIdx.x == 0) part[kNB + blockIdx.x] = cnt;
 }
 
+// ------------------------------------- Davidson of a small space in one workgroup
+
+// Spaces of up to kSmallDav determinants solve their Davidson in a single
+// launch of one 1024-thread workgroup: the same iteration as the host-driven
+// form (thick restart, flip-symmetric diagonal preconditioner, classical
+// Gram-Schmidt twice), with the small eigenproblem on one wavefront (the
+// one-wave parallel Jacobi) and every reduction in LDS, so a step costs one
+// launch and one read-back instead of several per iteration.  The
+// increments of an expansion run on concurrent streams, one CU each.
+constexpr int64_t kSmallDav = 1024;
+constexpr int kSmallThreads = 1024;
+
+struct SmallDav {
+  const int64_t* ptr;
+  const int32_t* col;
+  const double* val;
+  const double* diag;
+  const uint64_t* dets;
+  const int32_t* flip;
+  double* x;
+  double* Vb;
+  double* Sb;
+  double* r;
+  int64_t ld, n;
+  int m_max, max_dav, half;
+  double r_tol;
+  double* out;  // theta, residual norm, converged (0/1), iterations
+};
+
+__device__ void small_spmv(const SmallDav& a, const double* __restrict__ xin, double* __restrict__ y) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int64_t row = wave; row < a.n; row += nw) {
+    if (a.half && !canonical(a.dets[row])) continue;
+    double s = 0.0;
+    for (int64_t e = a.ptr[row] + lane; e < a.ptr[row + 1]; e += 64) s += a.val[e] * xin[a.col[e]];
+    s = wave_sum(s);
+    if (lane == 0) {
+      const double ya = s + a.diag[row] * xin[row];
+      y[row] = ya;
+      if (a.half) y[a.flip[row]] = ya;
+    }
+  }
+  __syncthreads();
+}
+
+// res[j] = sum over the workgroup of v[j], j < nv (v per thread, nv <= 17)
+__device__ __forceinline__ void small_sums(const double (&v)[kMaxM + 1], int nv, double* red, double* res) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int j = 0; j < kMaxM + 1; ++j)
+    if (j < nv) {
+      const double t = wave_sum(v[j]);
+      if (lane == 0) red[wave * (kMaxM + 1) + j] = t;
+    }
+  __syncthreads();
+  if ((int)threadIdx.x < nv) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += red[w * (kMaxM + 1) + threadIdx.x];
+    res[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kSmallThreads) hbci_dav_small_kernel(SmallDav a) {
+  __shared__ double Hs[256], A[256], Q[256], ev[16], yv[16], th[1];
+  __shared__ double red[(kSmallThreads / 64) * (kMaxM + 1)], res[kMaxM + 1];
+  __shared__ int perm[16];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t n = a.n, ld = a.ld;
+  double* Vb = a.Vb;
+  double* Sb = a.Sb;
+  for (int64_t i = tid; i < n; i += nt) Vb[i] = a.x[i];
+  for (int t = tid; t < 256; t += nt) Hs[t] = 0.0;
+  __syncthreads();
+  small_spmv(a, Vb, Sb);
+  {
+    double v[kMaxM + 1] = {};
+    for (int64_t i = tid; i < n; i += nt) v[0] += Vb[i] * Sb[i];
+    small_sums(v, 1, red, res);
+  }
+  if (tid == 0) Hs[0] = res[0];
+  __syncthreads();
+  int m = 1, conv = 0, it = 0;
+  double theta = res[0], rn = 1e300;
+  // Ritz pair of the current basis: x, r = H x - theta x, |r|
+  auto ritz = [&]() {
+    if (tid < 64) {
+      for (int t = tid; t < 256; t += 64) A[t] = Hs[t];
+      jacobi_lowest(A, Q, m, th, yv, ev, perm);
+    }
+    __syncthreads();
+    theta = th[0];
+    double v[kMaxM + 1] = {};
+    for (int64_t i = tid; i < n; i += nt) {
+      double xi = 0.0, wi = 0.0;
+      for (int j = 0; j < m; ++j) {
+        xi += yv[j] * Vb[j * ld + i];
+        wi += yv[j] * Sb[j * ld + i];
+      }
+      const double ri = wi - theta * xi;
+      a.x[i] = xi;
+      a.r[i] = ri;
+      v[0] += ri * ri;
+    }
+    small_sums(v, 1, red, res);
+    rn = sqrt(res[0]);
+  };
+  for (it = 0; it < a.max_dav; ++it) {
+    ritz();
+    if (rn <= a.r_tol) {
+      conv = 1;
+      break;
+    }
+    if (m == a.m_max) {  // thick restart, in place: each thread owns its entries of every vector
+      const int keep = a.m_max / 2 < kKeepRitz ? a.m_max / 2 : kKeepRitz;
+      for (int64_t i = tid; i < n; i += nt) {
+        double bv[kMaxM], bs[kMaxM];
+        for (int l = 0; l < kMaxM; ++l)
+          if (l < m) {
+            bv[l] = Vb[l * ld + i];
+            bs[l] = Sb[l * ld + i];
+          }
+        for (int j = 0; j < keep; ++j) {
+          double cv = 0.0, cs = 0.0;
+          for (int l = 0; l < kMaxM; ++l)
+            if (l < m) {
+              const double q = Q[l * 16 + perm[j]];
+              cv += q * bv[l];
+              cs += q * bs[l];
+            }
+          Vb[j * ld + i] = cv;
+          Sb[j * ld + i] = cs;
+        }
+      }
+      __syncthreads();
+      if (tid < 256) Hs[tid] = ((tid >> 4) == (tid & 15) && (tid & 15) < keep) ? ev[tid & 15] : 0.0;
+      __syncthreads();
+      m = keep;
+    }
+    // the correction, flip-symmetrised, into the next basis slot
+    double* T = Vb + m * ld;
+    for (int64_t i = tid; i < n; i += nt) {
+      double d1 = theta - a.diag[i];
+      if (fabs(d1) < 1e-10) d1 = d1 < 0.0 ? -1e-10 : 1e-10;
+      const int64_t f = a.flip[i];
+      double d2 = theta - a.diag[f];
+      if (fabs(d2) < 1e-10) d2 = d2 < 0.0 ? -1e-10 : 1e-10;
+      T[i] = 0.5 * (a.r[i] / d1 + a.r[f] / d2);
+    }
+    double t2 = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      double v[kMaxM + 1] = {};
+      for (int64_t i = tid; i < n; i += nt) {
+        const double ti = T[i];
+#pragma unroll
+        for (int j = 0; j < kMaxM; ++j)
+          if (j < m) v[j] += Vb[j * ld + i] * ti;
+      }
+      small_sums(v, m, red, res);
+      double w[kMaxM + 1] = {};
+      for (int64_t i = tid; i < n; i += nt) {
+        double ti = T[i];
+        for (int j = 0; j < m; ++j) ti -= res[j] * Vb[j * ld + i];
+        T[i] = ti;
+        w[0] += ti * ti;
+      }
+      if (pass == 1) {
+        small_sums(w, 1, red, res);
+        t2 = res[0];
+      } else {
+        __syncthreads();
+      }
+    }
+    if (!(t2 > 1e-28)) break;  // the space is exhausted
+    const double inv = 1.0 / sqrt(t2);
+    for (int64_t i = tid; i < n; i += nt) T[i] *= inv;
+    __syncthreads();
+    small_spmv(a, T, Sb + m * ld);
+    {
+      double v[kMaxM + 1] = {};
+      for (int64_t i = tid; i < n; i += nt) {
+        const double si = Sb[m * ld + i];
+#pragma unroll
+        for (int j = 0; j < kMaxM + 1; ++j)
+          if (j <= m) v[j] += Vb[j * ld + i] * si;
+      }
+      small_sums(v, m + 1, red, res);
+    }
+    if (tid <= m) {
+      Hs[tid * 16 + m] = res[tid];
+      Hs[m * 16 + tid] = res[tid];
+    }
+    __syncthreads();
+    ++m;
+  }
+  if (!conv) {  // ended on the iteration limit or an exhausted space: the Ritz pair of the basis
+    ritz();
+    conv = rn <= a.r_tol ? 1 : 0;
+  }
+  if (tid == 0) {
+    a.out[0] = theta;
+    a.out[1] = rn;
+    a.out[2] = conv;
+    a.out[3] = it;
+  }
+}
+
 // ---------------------------------------------------------------- host side
 
 int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
@@ -1142,6 +1349,21 @@ struct Run {
   // Davidson for the lowest root over the n keys from the unit,
   // flip-symmetric start vector in x; the Ritz vector is left in x.
   hipError_t davidson(int64_t n, double* theta_out, double* res_out, bool* conv) {
+    if (n <= kSmallDav) {
+      SmallDav a{at<int64_t>(L.ptr[cur]), at<int32_t>(L.col[cur]), at<double>(L.val[cur]), at<double>(L.diag),
+                 at<uint64_t>(L.dets), at<int32_t>(L.flip), at<double>(L.x), at<double>(L.basis),
+                 at<double>(L.sig), at<double>(L.r), o.max_det, n, o.m_max, o.max_dav, half, o.r_tol,
+                 at<double>(L.part)};
+      hipLaunchKernelGGL(hbci_dav_small_kernel, dim3(1), dim3(kSmallThreads), 0, st, a);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess) e = hipMemcpyAsync(pin, a.out, 4 * sizeof(double), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return e;
+      *theta_out = pin[0];
+      *res_out = pin[1];
+      *conv = pin[2] != 0.0;
+      return hipSuccess;
+    }
     double* Vb = at<double>(L.basis);
     double* Sb = at<double>(L.sig);
     double* x = at<double>(L.x);

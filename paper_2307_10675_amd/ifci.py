@@ -465,7 +465,7 @@ class Plan:
                                    _ptr(c), e_var, eps2, ctypes.byref(e2), ctypes.byref(n), _stream(stream)))
         return e2.value, n.value
 
-    def hbci_expansion(self, opts: HbciOptions | None = None, workers: int = 8, stream=None):
+    def hbci_expansion(self, opts: HbciOptions | None = None, workers: int = 16, stream=None):
         """Every increment by HBCI (E = E_var + E_PT2; ifci_hbci_solve_range
         with `workers` host threads), then the energy sums of eqs. 1-5:
         dict(results, energy, seconds)."""
