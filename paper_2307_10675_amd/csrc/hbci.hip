@@ -159,21 +159,28 @@ __device__ __forceinline__ void add_det(const Space& V, uint64_t key) {
   }
 }
 
-__device__ __forceinline__ void ext_add(uint64_t* ek, double* ev, uint64_t emask, int64_t cap, uint64_t key, double v,
+// A slot of the external table: the key and its N_a side by side, so that a
+// probe and the atomic update that follows touch one cache line.
+struct alignas(16) ExtSlot {
+  uint64_t key;
+  double val;
+};
+
+__device__ __forceinline__ void ext_add(ExtSlot* et, uint64_t emask, int64_t cap, uint64_t key, double v,
                                         HbciCtl* ctl) {
   uint64_t h = hmix(key) & emask;
   for (uint64_t n = 0; n <= emask; ++n) {
-    uint64_t kk = ek[h];
+    uint64_t kk = et[h].key;
     if (kk == kEmpty) {
-      kk = atomicCAS((unsigned long long*)(ek + h), (unsigned long long)kEmpty, (unsigned long long)key);
+      kk = atomicCAS((unsigned long long*)&et[h].key, (unsigned long long)kEmpty, (unsigned long long)key);
       if (kk == kEmpty) {
         if ((int64_t)atomicAdd(&ctl->n_ext, 1ull) >= cap) atomicOr(&ctl->flags, kFlagExtCap);
-        atomicAdd(ev + h, v);
+        atomicAdd(&et[h].val, v);
         return;
       }
     }
     if (kk == key) {
-      atomicAdd(ev + h, v);
+      atomicAdd(&et[h].val, v);
       return;
     }
     h = (h + 1) & emask;
@@ -398,6 +405,11 @@ __global__ void hbci_prep_kernel(const double* __restrict__ h, const double* __r
 
 __global__ void fill_u64_kernel(uint64_t* p, int64_t n, uint64_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void fill_slots_kernel(ExtSlot* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = ExtSlot{kEmpty, 0.0};
 }
 
 __global__ void fill_f64_kernel(double* p, int64_t n, double v) {
@@ -812,8 +824,8 @@ __global__ void __launch_bounds__(256) hbci_combo_kernel(const double* __restric
 // target is a representative.
 __global__ void __launch_bounds__(64 * kWaves) hbci_pt2_kernel(const double* __restrict__ ints, int k, const Space V,
                                                                const double* __restrict__ c, int64_t n, double eps,
-                                                               int half, uint64_t* __restrict__ ek,
-                                                               double* __restrict__ ev, uint64_t emask, int64_t ecap) {
+                                                               int half, ExtSlot* __restrict__ et, uint64_t emask,
+                                                               int64_t ecap) {
   const Lds s = load_lds(ints, k);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint8_t* L = s.lists + wave * 64;
@@ -837,22 +849,23 @@ __global__ void __launch_bounds__(64 * kWaves) hbci_pt2_kernel(const double* __r
           w = 2.0;  // i and flip(i) reach the flip-invariant a with equal terms
         }
       }
-      if (ht_find(V.keys, V.vals, V.mask, a) < 0) ext_add(ek, ev, emask, ecap, a, w * hc, V.ctl);
+      if (ht_find(V.keys, V.vals, V.mask, a) < 0) ext_add(et, emask, ecap, a, w * hc, V.ctl);
     }
   }
 }
 
 // part[block] = partial sum of N_a^2 / (e - H_aa); part[kNB + block] = count
 __global__ void __launch_bounds__(64 * kWaves) hbci_e2_kernel(const double* __restrict__ ints, int k,
-                                                      const uint64_t* __restrict__ ek, const double* __restrict__ ev,
+                                                      const ExtSlot* __restrict__ et,
                                                       int64_t ecap, double e, int half, double* __restrict__ part) {
   const Lds s = load_lds(ints, k);
   double* red = (double*)s.lists;  // no static LDS beside the dynamic block
   double sum = 0.0, cnt = 0.0;
   for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < ecap; h += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t key = ek[h];
+    const ExtSlot sl = et[h];
+    const uint64_t key = sl.key;
     if (key == kEmpty) continue;
-    const double na = ev[h];
+    const double na = sl.val;
     // a representative stands for itself and its partner
     const double w = (half && flip_key(key) != key) ? 2.0 : 1.0;
     sum += w * (na * na / (e - diag_val(s, k, (uint32_t)key, (uint32_t)(key >> 32))));
@@ -1083,7 +1096,7 @@ uint64_t pow2_at_least(int64_t x) {
 
 struct Layout {
   int64_t ints, ctl, part, bsum, dets, keys, vals, flip, diag, cnt, addc, pos, ptr[2], col[2], val[2], basis, sig, x, w,
-      r, t, keep, ek, ev;
+      r, t, keep, ext;
   int64_t bytes;
   uint64_t tcap, ecap;
 };
@@ -1124,8 +1137,7 @@ Layout layout(int k, const ifci_hbci_options& o) {
   L.r = take(D * 8);
   L.t = take(D * 8);
   L.keep = take((int64_t)2 * kKeepRitz * D * 8);
-  L.ek = take((int64_t)L.ecap * 8);
-  L.ev = take((int64_t)L.ecap * 8);
+  L.ext = take((int64_t)L.ecap * (int64_t)sizeof(ExtSlot));
   L.bytes = off;
   return L;
 }
@@ -1451,15 +1463,13 @@ struct Run {
   }
 
   hipError_t pt2(int64_t n, const double* c, double e_act, double eps2, double* e2, int64_t* n_ext) {
-    hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks((int64_t)L.ecap, 256, 4096)), dim3(256), 0, st,
-                       at<uint64_t>(L.ek), (int64_t)L.ecap, kEmpty);
-    hipLaunchKernelGGL(fill_f64_kernel, dim3(blocks((int64_t)L.ecap, 256, 4096)), dim3(256), 0, st, at<double>(L.ev),
-                       (int64_t)L.ecap, 0.0);
+    hipLaunchKernelGGL(fill_slots_kernel, dim3(blocks((int64_t)L.ecap, 256, 4096)), dim3(256), 0, st,
+                       at<ExtSlot>(L.ext), (int64_t)L.ecap);
     hipLaunchKernelGGL(hbci_pt2_kernel, dim3(blocks(n, kWaves, 8192)), dim3(64 * kWaves), lds, st,
-                       at<double>(L.ints), I.k, space(), c, n, eps2, half, at<uint64_t>(L.ek), at<double>(L.ev),
-                       L.ecap - 1, o.max_ext);
-    hipLaunchKernelGGL(hbci_e2_kernel, dim3(kNB), dim3(64 * kWaves), lds, st, at<double>(L.ints), I.k, at<uint64_t>(L.ek),
-                       at<double>(L.ev), (int64_t)L.ecap, e_act, half, at<double>(L.part));
+                       at<double>(L.ints), I.k, space(), c, n, eps2, half, at<ExtSlot>(L.ext), L.ecap - 1,
+                       o.max_ext);
+    hipLaunchKernelGGL(hbci_e2_kernel, dim3(kNB), dim3(64 * kWaves), lds, st, at<double>(L.ints), I.k,
+                       at<ExtSlot>(L.ext), (int64_t)L.ecap, e_act, half, at<double>(L.part));
     hipError_t e = hipGetLastError();
     double s[2];
     if (e == hipSuccess) e = read_parts(2, s);
