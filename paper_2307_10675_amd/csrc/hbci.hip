@@ -732,16 +732,19 @@ __global__ void __launch_bounds__(256) hbci_spmv_kernel(const int64_t* __restric
 }
 
 // part[j][block] = partial of B_j . v, j < m
+// part[row0 + j][block] = partial of B_j . v, j < m; with self, row
+// row0 + m holds the partial of v . v
 __global__ void __launch_bounds__(256) hbci_dots_kernel(const double* __restrict__ B, int64_t ld, int m,
                                                         const double* __restrict__ v, int64_t n,
-                                                        double* __restrict__ part) {
+                                                        double* __restrict__ part, int row0, int self) {
   __shared__ double red[4];
-  for (int j = 0; j < m; ++j) {
+  for (int j = 0; j < m + self; ++j) {
+    const double* b = j < m ? B + j * ld : v;
     double s = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-      s += B[j * ld + i] * v[i];
+      s += b[i] * v[i];
     s = group_sum(s, red);
-    if (threadIdx.x == 0) part[j * kNB + blockIdx.x] = s;
+    if (threadIdx.x == 0) part[(row0 + j) * kNB + blockIdx.x] = s;
   }
 }
 
@@ -1353,7 +1356,8 @@ struct Run {
   }
 
   hipError_t dots(const double* B, int m, const double* v, int64_t n, double* out) {
-    hipLaunchKernelGGL(hbci_dots_kernel, dim3(kNB), dim3(256), 0, st, B, o.max_det, m, v, n, at<double>(L.part));
+    hipLaunchKernelGGL(hbci_dots_kernel, dim3(kNB), dim3(256), 0, st, B, o.max_det, m, v, n, at<double>(L.part), 0,
+                       0);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? read_parts(m, out) : e;
   }
@@ -1394,20 +1398,27 @@ struct Run {
     int m = 1;
     double theta = hv[0], rn = INFINITY;
     *conv = false;
+    // Per iteration three read-backs: the residual norm with the first
+    // Gram-Schmidt overlaps (the correction is formed before the
+    // convergence test is known, and dropped if it passes), the second
+    // overlaps with the correction's norm (|t - V d|^2 = |t|^2 - |d|^2 for an
+    // orthonormal V), and the new column of the subspace matrix.
+    double* part = at<double>(L.part);
+    double rd[kParts];
     for (int it = 0; it < o.max_dav; ++it) {
       Coef y{};
       lowest_eigen(Hs, m, &theta, y.v);
-      hipLaunchKernelGGL(hbci_ritz_kernel, dim3(kNB), dim3(256), 0, st, Vb, Sb, ld, m, y, theta, x, w, r, n,
-                         at<double>(L.part));
+      hipLaunchKernelGGL(hbci_ritz_kernel, dim3(kNB), dim3(256), 0, st, Vb, Sb, ld, m, y, theta, x, w, r, n, part);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      double r2;
-      if ((e = read_parts(1, &r2)) != hipSuccess) return e;
-      rn = std::sqrt(r2);
-      if (rn <= o.r_tol) {
-        *conv = true;
-        break;
-      }
-      if (m == o.m_max) {  // thick restart: the lowest Ritz vectors and their sigmas
+      if (m == o.m_max) {
+        double r2;
+        if ((e = read_parts(1, &r2)) != hipSuccess) return e;
+        rn = std::sqrt(r2);
+        if (rn <= o.r_tol) {
+          *conv = true;
+          break;
+        }
+        // thick restart: the lowest Ritz vectors and their sigmas
         const int keep = std::min(kKeepRitz, o.m_max / 2);
         double ev[kMaxM], Y[kMaxM][kMaxM];
         sym_eigen(Hs, m, ev, Y);
@@ -1430,14 +1441,33 @@ struct Run {
       }
       hipLaunchKernelGGL(hbci_precond_kernel, dim3(gb), dim3(256), 0, st, r, at<double>(L.diag),
                          at<int32_t>(L.flip), theta, t, n);
-      double t2 = 0.0;
-      for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
-        Coef d{};
-        if ((e = dots(Vb, m, t, n, d.v)) != hipSuccess) return e;
-        hipLaunchKernelGGL(hbci_orth_kernel, dim3(kNB), dim3(256), 0, st, Vb, ld, m, d, t, n, at<double>(L.part));
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(hbci_dots_kernel, dim3(kNB), dim3(256), 0, st, Vb, ld, m, t, n, part, 1, 0);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if ((e = read_parts(m + 1, rd)) != hipSuccess) return e;  // row 0: |r|^2 of this Ritz pair
+      rn = std::sqrt(rd[0]);
+      if (rn <= o.r_tol) {
+        *conv = true;
+        break;
       }
-      if ((e = read_parts(1, &t2)) != hipSuccess) return e;
+      Coef d{};
+      for (int j = 0; j < m; ++j) d.v[j] = rd[j + 1];
+      hipLaunchKernelGGL(hbci_orth_kernel, dim3(kNB), dim3(256), 0, st, Vb, ld, m, d, t, n, part);
+      hipLaunchKernelGGL(hbci_dots_kernel, dim3(kNB), dim3(256), 0, st, Vb, ld, m, t, n, part, 0, 1);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if ((e = read_parts(m + 1, rd)) != hipSuccess) return e;
+      Coef d2{};
+      double dd = 0.0;
+      for (int j = 0; j < m; ++j) {
+        d2.v[j] = rd[j];
+        dd += rd[j] * rd[j];
+      }
+      const double tt = rd[m];
+      hipLaunchKernelGGL(hbci_orth_kernel, dim3(kNB), dim3(256), 0, st, Vb, ld, m, d2, t, n, part);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      double t2 = tt - dd;
+      if (!(t2 > 1e-6 * tt)) {  // cancellation: the norm as summed by the second pass
+        if ((e = read_parts(1, &t2)) != hipSuccess) return e;
+      }
       if (!(t2 > 1e-28)) break;  // the space is exhausted
       hipLaunchKernelGGL(hbci_scale_kernel, dim3(gb), dim3(256), 0, st, t, 1.0 / std::sqrt(t2), Vb + m * ld, n);
       if ((e = spmv(Vb + m * ld, Sb + m * ld, n)) != hipSuccess) return e;
