@@ -166,15 +166,21 @@ struct alignas(16) ExtSlot {
   double val;
 };
 
-__device__ __forceinline__ void ext_add(ExtSlot* et, uint64_t emask, int64_t cap, uint64_t key, double v,
-                                        HbciCtl* ctl) {
+// (each slot taken is listed in elist, so that the final sum visits the
+// filled slots only)
+__device__ __forceinline__ void ext_add(ExtSlot* et, int64_t* elist, uint64_t emask, int64_t cap, uint64_t key,
+                                        double v, HbciCtl* ctl) {
   uint64_t h = hmix(key) & emask;
   for (uint64_t n = 0; n <= emask; ++n) {
     uint64_t kk = et[h].key;
     if (kk == kEmpty) {
       kk = atomicCAS((unsigned long long*)&et[h].key, (unsigned long long)kEmpty, (unsigned long long)key);
       if (kk == kEmpty) {
-        if ((int64_t)atomicAdd(&ctl->n_ext, 1ull) >= cap) atomicOr(&ctl->flags, kFlagExtCap);
+        const int64_t at = (int64_t)atomicAdd(&ctl->n_ext, 1ull);
+        if (at < cap)
+          elist[at] = (int64_t)h;
+        else
+          atomicOr(&ctl->flags, kFlagExtCap);
         atomicAdd(&et[h].val, v);
         return;
       }
@@ -827,7 +833,8 @@ __global__ void __launch_bounds__(256) hbci_combo_kernel(const double* __restric
 // target is a representative.
 __global__ void __launch_bounds__(64 * kWaves) hbci_pt2_kernel(const double* __restrict__ ints, int k, const Space V,
                                                                const double* __restrict__ c, int64_t n, double eps,
-                                                               int half, ExtSlot* __restrict__ et, uint64_t emask,
+                                                               int half, ExtSlot* __restrict__ et,
+                                                               int64_t* __restrict__ elist, uint64_t emask,
                                                                int64_t ecap) {
   const Lds s = load_lds(ints, k);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -852,7 +859,7 @@ __global__ void __launch_bounds__(64 * kWaves) hbci_pt2_kernel(const double* __r
           w = 2.0;  // i and flip(i) reach the flip-invariant a with equal terms
         }
       }
-      if (ht_find(V.keys, V.vals, V.mask, a) < 0) ext_add(et, emask, ecap, a, w * hc, V.ctl);
+      if (ht_find(V.keys, V.vals, V.mask, a) < 0) ext_add(et, elist, emask, ecap, a, w * hc, V.ctl);
     }
   }
 }
@@ -860,14 +867,17 @@ __global__ void __launch_bounds__(64 * kWaves) hbci_pt2_kernel(const double* __r
 // part[block] = partial sum of N_a^2 / (e - H_aa); part[kNB + block] = count
 __global__ void __launch_bounds__(64 * kWaves) hbci_e2_kernel(const double* __restrict__ ints, int k,
                                                       const ExtSlot* __restrict__ et,
-                                                      int64_t ecap, double e, int half, double* __restrict__ part) {
+                                                      const int64_t* __restrict__ elist, int64_t cap,
+                                                      const HbciCtl* __restrict__ ctl, double e, int half,
+                                                      double* __restrict__ part) {
   const Lds s = load_lds(ints, k);
   double* red = (double*)s.lists;  // no static LDS beside the dynamic block
+  const int64_t n_filled = (int64_t)ctl->n_ext < cap ? (int64_t)ctl->n_ext : cap;
   double sum = 0.0, cnt = 0.0;
-  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < ecap; h += (int64_t)gridDim.x * blockDim.x) {
-    const ExtSlot sl = et[h];
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_filled;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const ExtSlot sl = et[elist[t]];
     const uint64_t key = sl.key;
-    if (key == kEmpty) continue;
     const double na = sl.val;
     // a representative stands for itself and its partner
     const double w = (half && flip_key(key) != key) ? 2.0 : 1.0;
@@ -1099,7 +1109,7 @@ uint64_t pow2_at_least(int64_t x) {
 
 struct Layout {
   int64_t ints, ctl, part, bsum, dets, keys, vals, flip, diag, cnt, addc, pos, ptr[2], col[2], val[2], basis, sig, x, w,
-      r, t, keep, ext;
+      r, t, keep, ext, elist;
   int64_t bytes;
   uint64_t tcap, ecap;
 };
@@ -1141,6 +1151,7 @@ Layout layout(int k, const ifci_hbci_options& o) {
   L.t = take(D * 8);
   L.keep = take((int64_t)2 * kKeepRitz * D * 8);
   L.ext = take((int64_t)L.ecap * (int64_t)sizeof(ExtSlot));
+  L.elist = take(o.max_ext * 8);
   L.bytes = off;
   return L;
 }
@@ -1496,10 +1507,11 @@ struct Run {
     hipLaunchKernelGGL(fill_slots_kernel, dim3(blocks((int64_t)L.ecap, 256, 4096)), dim3(256), 0, st,
                        at<ExtSlot>(L.ext), (int64_t)L.ecap);
     hipLaunchKernelGGL(hbci_pt2_kernel, dim3(blocks(n, kWaves, 8192)), dim3(64 * kWaves), lds, st,
-                       at<double>(L.ints), I.k, space(), c, n, eps2, half, at<ExtSlot>(L.ext), L.ecap - 1,
-                       o.max_ext);
+                       at<double>(L.ints), I.k, space(), c, n, eps2, half, at<ExtSlot>(L.ext),
+                       at<int64_t>(L.elist), L.ecap - 1, o.max_ext);
     hipLaunchKernelGGL(hbci_e2_kernel, dim3(kNB), dim3(64 * kWaves), lds, st, at<double>(L.ints), I.k,
-                       at<ExtSlot>(L.ext), (int64_t)L.ecap, e_act, half, at<double>(L.part));
+                       at<ExtSlot>(L.ext), at<int64_t>(L.elist), o.max_ext, at<HbciCtl>(L.ctl), e_act, half,
+                       at<double>(L.part));
     hipError_t e = hipGetLastError();
     double s[2];
     if (e == hipSuccess) e = read_parts(2, s);
