@@ -726,9 +726,21 @@ __global__ void __launch_bounds__(256) hbci_spmv_kernel(const int64_t* __restric
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
   for (int64_t a = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; a < n; a += nw) {
     if (flip && !canonical(dets[a])) continue;
-    double s = 0.0;
-    for (int64_t e = ptr[a] + lane; e < ptr[a + 1]; e += 64) s += val[e] * x[col[e]];
-    s = wave_sum(s);
+    // four entries per lane in flight: their column and value loads, then
+    // the four gathers, are independent of each other
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    const int64_t end = ptr[a + 1];
+    int64_t e = ptr[a] + lane;
+    for (; e + 192 < end; e += 256) {
+      const int32_t c0 = col[e], c1 = col[e + 64], c2 = col[e + 128], c3 = col[e + 192];
+      const double v0 = val[e], v1 = val[e + 64], v2 = val[e + 128], v3 = val[e + 192];
+      s0 += v0 * x[c0];
+      s1 += v1 * x[c1];
+      s2 += v2 * x[c2];
+      s3 += v3 * x[c3];
+    }
+    for (; e < end; e += 64) s0 += val[e] * x[col[e]];
+    double s = wave_sum((s0 + s1) + (s2 + s3));
     if (lane == 0) {
       const double ya = s + diag[a] * x[a];
       y[a] = ya;
