@@ -135,10 +135,6 @@ typedef __attribute__((address_space(3))) double lds_double;
 __device__ __forceinline__ void lds_add(double* p, double v) {
   __atomic_fetch_add((lds_double*)p, v, __ATOMIC_RELAXED);
 }
-typedef __attribute__((address_space(3))) float lds_float;
-__device__ __forceinline__ void lds_add(float* p, float v) {
-  __atomic_fetch_add((lds_float*)p, v, __ATOMIC_RELAXED);
-}
 
 constexpr double kSqrt2 = 1.4142135623730950488;
 constexpr double kRSqrt2 = 0.70710678118654752440;

@@ -407,11 +407,14 @@ __global__ void __launch_bounds__(col_threads<T>()) sigma_column_kernel(IncDev d
 // 16 orbitals (12,870 strings, 136 pairs) do not fit that LDS layout.  The
 // split variant keeps the same scheme with the column copy left in L2 (the
 // alpha values are read from C, kBD k-steps ahead like the beta values).
-// FP32 keeps all A fragments in LDS (one pass) with an FP32 accumulator (its
-// atomic order is not fixed: repeated products agree to FP32 rounding); FP64
-// keeps an FP64 accumulator and takes the fragments in passes of MTP row
-// tiles (each pass sweeps every tile of the column and rebuilds D; the MFMA
-// work is not repeated).
+// Both precisions keep an FP64 accumulator (103 KB) and take the fragments in
+// passes of MTP row tiles (each pass sweeps every tile of the column and
+// rebuilds D; the MFMA work is not repeated): FP32 in two passes of 5 + 4
+// tiles, FP64 in three of 3.  An FP32 accumulator would leave room for all
+// nine FP32 tiles in one pass, but its LDS atomics (ds_add_f32) cost more
+// than the second pass: 16o16e FP32 95.5 ms in one pass against 85.8 ms in
+// two with ds_add_f64 (waves waiting to issue LDS instructions: 20 % of wave
+// time against under 1 %).
 template <typename T, int K>
 struct ColSplit {
   static constexpr int NP = K * (K + 1) / 2;
@@ -420,10 +423,10 @@ struct ColSplit {
   static constexpr int KS2 = (KS + 1) / 2;
   static constexpr int N = max_strings(K);
   static constexpr bool kF32 = sizeof(T) == 4;
-  static constexpr int MTP = kF32 ? MT : 3;                // row tiles per pass
+  static constexpr int MTP = kF32 ? 5 : 3;                // row tiles per pass
   static constexpr int NPASS = (MT + MTP - 1) / MTP;
   static constexpr int KSP = kF32 ? 2 * KS2 : KS;         // k-steps stored per row tile
-  typedef typename std::conditional<kF32, float, double>::type SA;  // accumulator
+  typedef double SA;  // accumulator
   static constexpr int64_t vf_bytes = (int64_t)MTP * KSP * 64 * sizeof(T);
   static constexpr int64_t col_bytes = 0;
   static constexpr int64_t s_bytes = ((int64_t)N * sizeof(SA) + 15) / 16 * 16;
@@ -432,8 +435,7 @@ struct ColSplit {
 };
 
 // Three waves per SIMD in both precisions; FP32 with a shorter load
-// lookahead (fits the registers of its single pass).  FP64 with three waves
-// instead of two: 16o16e 155 -> 140 ms.
+// lookahead.  FP64 with three waves instead of two: 16o16e 155 -> 140 ms.
 template <typename T>
 constexpr int split_threads() { return 768; }
 
@@ -475,21 +477,32 @@ __device__ __forceinline__ void column_split_body(const int32_t* __restrict__ pt
       const bool jv = jr < N;
       const int J = jv ? jr : N - 1;
       constexpr int kBD = sizeof(T) == 4 ? 6 : 8;  // loads run kBD k-steps ahead of their use
-      int32_t ent[KS];
+      // table entries (J + neg (N + 1) <= 2 N < 2^16), two k-steps per register
+      constexpr int KE = (KS + 1) / 2;
+      uint32_t entp[KE];
       T vb[KS], vaq[KS];
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const int Q = 4 * s + kq;
-        ent[s] = Q < NP ? (int)ptabT[Q * N + J] : N;
+      for (int h = 0; h < KE; ++h) {
+        const int Q0 = 8 * h + kq, Q1 = Q0 + 4;
+        const uint32_t e0 = Q0 < NP ? (uint16_t)ptabT[Q0 * N + J] : (uint32_t)N;
+        const uint32_t e1 = Q1 < NP ? (uint16_t)ptabT[Q1 * N + J] : (uint32_t)N;
+        entp[h] = e0 | (e1 << 16);
       }
+      auto ent = [&](int s) -> int { return (int)((entp[s >> 1] >> (16 * (s & 1))) & 0xffffu); };
       auto beta = [&](int s) -> T { return cf[(int64_t)browl[4 * s + kq] + jr]; };
-      // alpha value C[J1][b] signed, J1 + neg (N + 1) = ent (N: no link)
+      // alpha value C[J1][b] (J1 + neg (N + 1) = ent, N: no link), loaded
+      // unconditionally (from entry 0 where there is no link) and used times
+      // afac(s) = +-1 or 0 at its k-step, so that no branch splits the stream
+      // of loads and the waits can count them exactly
       auto alpha = [&](int s) -> T {
-        const int e = ent[s];
+        const int e = ent(s);
+        const int j1 = e > N ? e - (N + 1) : e;
+        return crow[j1 < N ? j1 : 0];
+      };
+      auto afac = [&](int s) -> T {
+        const int e = ent(s);
         const bool ng = e > N;
-        const int j1 = ng ? e - (N + 1) : e;
-        const T v = j1 < N ? crow[j1] : (T)0;
-        return ng ? -v : v;
+        return (ng ? e - (N + 1) : e) < N ? (ng ? (T)-1 : (T)1) : (T)0;
       };
 #pragma unroll
       for (int s = 0; s < kBD && s < KS; ++s) {
@@ -502,7 +515,7 @@ __device__ __forceinline__ void column_split_body(const int32_t* __restrict__ pt
       float2 af[MP];
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        const T bop = fma_t(bsgl[4 * s + kq], vb[s], vaq[s]);
+        const T bop = fma_t(bsgl[4 * s + kq], vb[s], vaq[s] * afac(s));
         if (s + kBD < KS) {
           vb[s + kBD] = beta(s + kBD);
           vaq[s + kBD] = alpha(s + kBD);
@@ -534,7 +547,7 @@ __device__ __forceinline__ void column_split_body(const int32_t* __restrict__ pt
           for (int r = 0; r < 4; ++r) {
             const int sp = 4 * (m0 + m) + r;
             if (sp < KS && 4 * sp + kq < NP) {
-              const int e = ent[sp];
+              const int e = ent(sp);
               if (e != N) {
                 const bool ng = e > N;
                 const SA v = (SA)acc[m][r];

@@ -79,9 +79,9 @@ def test_column_sigma_repeatable():
 
 def test_column_sigma_rows_16_orbitals():
     """16o16e (165,636,900 determinants): the split column kernel (fragments
-    in passes; FP32 accumulates in FP32) on 24 sampled rows against the
-    oracle's Slater-Condon rows; the general product is unsupported at this
-    size and says so."""
+    in passes, an FP64 accumulator in both precisions) on 24 sampled rows
+    against the oracle's Slater-Condon rows, and repeatable to FP64 rounding;
+    the general product is unsupported at this size and says so."""
     import torch
     print("[column] 16o16e rows", flush=True)
     n, K, seed = 16, 32, 4216
@@ -101,8 +101,13 @@ def test_column_sigma_rows_16_orbitals():
     big = max(1.0, np.abs(want).max())
     c = torch.tensor(cp, device="cuda")
     for prec, tol in ((ifci.FP64, 1e-12 * n), (ifci.MIXED, 2e-5)):
-        got = plan.sigma_sector(0, c, precision=prec)[torch.tensor(idx, device="cuda")].cpu().numpy()
+        x = plan.sigma_sector(0, c, precision=prec)
+        got = x[torch.tensor(idx, device="cuda")].cpu().numpy()
         assert np.abs(got - ref).max() <= tol * big, (prec, np.abs(got - ref).max())
+        # a second product agrees to FP64 rounding (the scatter's order is not fixed)
+        y = plan.sigma_sector(0, c, precision=prec)
+        assert float((x - y).abs().max()) <= 1e-13 * float(x.abs().max()), prec
+        del x, y
     full = torch.zeros(n_str * n_str, dtype=torch.float64, device="cuda")
     with pytest.raises(ifci.IfciError) as e:
         plan.sigma(0, full)
