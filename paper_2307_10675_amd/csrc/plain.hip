@@ -18,7 +18,7 @@ namespace ifci {
 
 __global__ void __launch_bounds__(256) sym_combine_kernel(IncDev d, const double* __restrict__ Sm,
                                                           double* __restrict__ sig) {
-  sym_combine_body(d, Sm, sig, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  sym_combine_body(d, Sm, sig, blockIdx.x, gridDim.x);
 }
 
 bool sigma_column_supported(const IncDev& d) {
@@ -54,7 +54,7 @@ static hipError_t launch_column_k(const IncDev& d, const double* V, const int32_
   hipLaunchKernelGGL((expand_sym_kernel<T>), dim3(2048), dim3(256), 0, st, d, c, cf);
   hipLaunchKernelGGL((sigma_column_kernel<T, K>), dim3(n), dim3(col_threads<T>()), (unsigned)SH::lds, st, d, V, ptab,
                      ptabT, (const T*)cf, (const T*)vfg, Sm);
-  hipLaunchKernelGGL(sym_combine_kernel, dim3((unsigned)((d.n_sym + 255) / 256)), dim3(256), 0, st, d, Sm, sig);
+  hipLaunchKernelGGL(sym_combine_kernel, dim3(4096), dim3(256), 0, st, d, Sm, sig);
   return hipGetLastError();
 }
 
@@ -75,7 +75,7 @@ static hipError_t launch_column_split(const IncDev& d, const double* V, const in
   hipLaunchKernelGGL((expand_sym_kernel<T>), dim3(4096), dim3(256), 0, st, d, c, cf);
   hipLaunchKernelGGL((sigma_column_split_kernel<T, K>), dim3(n), dim3(split_threads<T>()), (unsigned)SH::lds, st, d,
                      ptab, ptabT, (const T*)cf, (const T*)vfg, Sm);
-  hipLaunchKernelGGL(sym_combine_kernel, dim3((unsigned)((d.n_sym + 255) / 256)), dim3(256), 0, st, d, Sm, sig);
+  hipLaunchKernelGGL(sym_combine_kernel, dim3(4096), dim3(256), 0, st, d, Sm, sig);
   return hipGetLastError();
 }
 

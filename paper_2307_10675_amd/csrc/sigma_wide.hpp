@@ -210,21 +210,44 @@ struct ColShape {
 };
 
 // Packed scaled symmetric c -> full unscaled C [(n + 1) x n] of T (row n and
-// a tail of 16 entries zero).
+// a tail of 16 entries zero), in 32 x 32 tiles, grid-strided over the tiles
+// blk, blk + nblk, ...  (256 threads).  Entry (r, cc) is c[tri(cc) + r] above
+// the diagonal and c[tri(r) + cc] on and below it; tiles wholly above the
+// diagonal are read along r into LDS and written along cc, so both the reads
+// of c and the writes of C are coalesced.
 template <typename T>
 __device__ __forceinline__ void expand_sym_body(int n, const double* __restrict__ c, T* __restrict__ cf, int blk,
                                                 int nblk) {
-  const int64_t total = (int64_t)(n + 1) * n + 16;
-  for (int64_t i = (int64_t)blk * blockDim.x + threadIdx.x; i < total; i += (int64_t)nblk * blockDim.x) {
-    const int64_t r = i / n;
-    const int cc = (int)(i - r * n);
-    double v = 0.0;
-    if (r < n) {
-      const int a = (int)r;
-      v = c[packed(a, cc)];
-      if (a != cc) v *= kRSqrt2;
+  __shared__ double tl[32][33];
+  const int tc = (n + 31) / 32;
+  const int64_t nt = (int64_t)((n + 32) / 32) * tc;  // (n + 1) rows
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  if (blk == 0 && threadIdx.x < 16) cf[(int64_t)(n + 1) * n + threadIdx.x] = (T)0;
+  for (int64_t t = blk; t < nt; t += nblk) {
+    const int r0 = (int)(t / tc) * 32, c0 = (int)(t % tc) * 32;
+    if (r0 + 32 <= c0) {
+      for (int k = ty; k < 32; k += 8) {
+        const int cc = c0 + k;
+        tl[k][tx] = cc < n ? c[tri(cc) + r0 + tx] : 0.0;
+      }
+      __syncthreads();
+      for (int k = ty; k < 32; k += 8) {
+        const int cc = c0 + tx;
+        if (cc < n) cf[(int64_t)(r0 + k) * n + cc] = (T)(tl[tx][k] * kRSqrt2);
+      }
+      __syncthreads();
+    } else {
+      for (int k = ty; k < 32; k += 8) {
+        const int r = r0 + k, cc = c0 + tx;
+        if (r > n || cc >= n) continue;
+        double v = 0.0;
+        if (r < n) {
+          v = c[packed(r, cc)];
+          if (r != cc) v *= kRSqrt2;
+        }
+        cf[(int64_t)r * n + cc] = (T)v;
+      }
     }
-    cf[i] = (T)v;
   }
 }
 
@@ -571,14 +594,38 @@ __global__ void __launch_bounds__(split_threads<T>()) sigma_column_split_kernel(
   column_split_body<T, K>(ptab, ptabT, cf, vfg, Sm, blockIdx.x, lds);
 }
 
-// sigma (packed scaled) = S + S^T from Sm[b][a] = S[a][b].
+// sigma (packed scaled) = S + S^T from Sm[b][a] = S[a][b], in 32 x 32 tiles
+// (ta <= tb) of the upper triangle, grid-strided over the tiles blk, blk +
+// nblk, ...  (256 threads).  Sm[a][b] is read along b into LDS; Sm[b][a] and
+// sigma[tri(b) + a] along a.
+__device__ __forceinline__ int64_t sym_combine_tiles(int n) {
+  const int64_t t = (n + 31) / 32;
+  return t * (t + 1) / 2;
+}
 __device__ __forceinline__ void sym_combine_body(const IncDev& d, const double* __restrict__ Sm,
-                                                 double* __restrict__ sig, int64_t i) {
-  if (i >= d.n_sym) return;
-  int a, b;
-  unpack(i, &a, &b);
-  const int64_t n = d.n_str;
-  sig[i] = a == b ? 2.0 * Sm[(int64_t)a * n + a] : kSqrt2 * (Sm[(int64_t)b * n + a] + Sm[(int64_t)a * n + b]);
+                                                 double* __restrict__ sig, int64_t blk, int64_t nblk) {
+  __shared__ double tl[32][33];
+  const int n = d.n_str;
+  const int64_t nt = sym_combine_tiles(n);
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int64_t t = blk; t < nt; t += nblk) {
+    int ta, tb;
+    unpack(t, &ta, &tb);
+    const int a0 = 32 * ta, b0 = 32 * tb;
+    for (int k = ty; k < 32; k += 8) {
+      const int a = a0 + k, b = b0 + tx;
+      tl[k][tx] = (a < n && b < n) ? Sm[(int64_t)a * n + b] : 0.0;
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+      const int a = a0 + tx, b = b0 + k;
+      if (a <= b && b < n) {
+        const double y = Sm[(int64_t)b * n + a];
+        sig[tri(b) + a] = a == b ? 2.0 * y : kSqrt2 * (y + tl[tx][k]);
+      }
+    }
+    __syncthreads();
+  }
 }
 
 

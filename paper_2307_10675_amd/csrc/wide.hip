@@ -193,9 +193,10 @@ __global__ void __launch_bounds__(kVecThreads) wb_expand_kernel(WideItem* const*
                                                                 int which) {
   const int nl = live_count(ctl, which);
   const int* lst = live_list(ctl, cap, which);
-  const int per = kVecGrid;  // blocks per increment, grid-strided inside
-  const int nb = (int)(((int64_t)(it[0]->d.n_str + 1) * it[0]->d.n_str + 16 + kVecThreads - 1) / kVecThreads);
-  const int units = nb < per ? nb : per;
+  const int per = kVecGrid;  // blocks per increment, grid-strided inside over 32 x 32 tiles
+  const int n = it[0]->d.n_str;
+  const int64_t nb = (int64_t)((n + 32) / 32) * ((n + 31) / 32);
+  const int units = nb < per ? (int)nb : per;
   for (int u = blockIdx.x; u < nl * units; u += gridDim.x) {
     const WideItem* w = it[lst[u / units]];
     const DavState* S = st(w);
@@ -250,12 +251,12 @@ __global__ void __launch_bounds__(split_threads<T>()) wb_column_split_kernel(Wid
 __global__ void __launch_bounds__(kVecThreads) wb_combine_kernel(WideItem* const* it, const int* ctl, int cap) {
   const int nl = live_count(ctl, 0);
   const int* lst = live_list(ctl, cap, 0);
-  const int per = (int)((it[0]->d.n_sym + kVecThreads - 1) / kVecThreads);
+  const int64_t nt = sym_combine_tiles(it[0]->d.n_str);
+  const int per = nt < kVecGrid ? (int)nt : kVecGrid;  // blocks per increment, grid-strided inside
   for (int64_t u = blockIdx.x; u < (int64_t)nl * per; u += gridDim.x) {
     const WideItem* w = it[lst[u / per]];
     const DavState* S = st(w);
-    sym_combine_body(w->d, w->sc + col_scratch(w->d).sm, w->Sb + (int64_t)S->m * w->d.stride,
-                     (u % per) * kVecThreads + threadIdx.x);
+    sym_combine_body(w->d, w->sc + col_scratch(w->d).sm, w->Sb + (int64_t)S->m * w->d.stride, u % per, per);
   }
 }
 
