@@ -123,6 +123,6 @@ def test_autograd_function():
     e = ifci_energy(h, eri, p, r_tol=1e-10)
     e.backward()
     e_o, dh_o, dg_o = ordm.ifci_gradient(p)
-    assert abs(float(e) - e_o) <= 1e-9
+    assert abs(float(e.detach()) - e_o) <= 1e-9
     assert np.abs(h.grad.cpu().numpy() - dh_o).max() <= 1e-8
     assert np.abs(eri.grad.cpu().numpy() - dg_o).max() <= 1e-8
