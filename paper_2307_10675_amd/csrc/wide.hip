@@ -205,11 +205,20 @@ __global__ void __launch_bounds__(kVecThreads) wb_expand_kernel(WideItem* const*
   }
 }
 
+// Workgroup shape of the batched column kernel.  A 10-orbital column has 16
+// tiles of 16 strings: 4 waves take them in 4 equal rounds (12 waves would
+// leave 8 idle in the second), and 4 (FP32) or 3 (FP64) such workgroups share
+// a CU; larger columns keep the 12 waves of the single-increment kernel.
+template <typename T, int K>
+constexpr int wide_col_threads() { return K <= 10 ? 256 : col_threads<T>(); }
+template <typename T, int K>
+constexpr int wide_col_waves() { return K <= 10 ? (sizeof(T) == 4 ? 4 : 3) : 3; }  // per SIMD
+
 // Column sigma over (increment, beta string) units: each workgroup takes a
 // contiguous range of units, so it reloads the fragment image only where its
 // range crosses into the next increment.
 template <typename T, int K>
-__global__ void __launch_bounds__(col_threads<T>()) wb_column_kernel(WideItem* const* it, const int* ctl, int cap,
+__global__ void __launch_bounds__((wide_col_threads<T, K>()), (wide_col_waves<T, K>())) wb_column_kernel(WideItem* const* it, const int* ctl, int cap,
                                                                      int which) {
   extern __shared__ __align__(16) char lds[];
   const int nl = live_count(ctl, which);
@@ -445,9 +454,15 @@ hipError_t column_sigma(const WideRun& R, int which, hipStream_t s) {
   if constexpr (K <= 14) {
     typedef ColShape<T, K> SH;
     static_assert(SH::lds <= kMaxLds, "column sigma LDS");
-    const int per_cu = SH::lds <= kMaxLds / 2 ? 2 : 1;
-    hipLaunchKernelGGL((wb_column_kernel<T, K>), dim3(256 * per_cu), dim3(col_threads<T>()), (unsigned)SH::lds, s,
-                       R.items, R.ctl, n, which);
+    constexpr int kThreads = wide_col_threads<T, K>();
+    // workgroups per CU: at 10 orbitals the resident count (by waves, 4 SIMDs
+    // x waves each, and by LDS), else two where the LDS would hold two
+    constexpr int by_waves = 4 * wide_col_waves<T, K>() / (kThreads / 64);
+    constexpr int by_lds = (int)(kMaxLds / SH::lds);
+    constexpr int per_cu = K <= 10 ? (by_waves < by_lds ? by_waves : by_lds) : (SH::lds <= kMaxLds / 2 ? 2 : 1);
+    static_assert(per_cu >= 1, "column sigma residency");
+    hipLaunchKernelGGL((wb_column_kernel<T, K>), dim3(256 * per_cu), dim3(kThreads), (unsigned)SH::lds, s, R.items,
+                       R.ctl, n, which);
   } else {
     typedef ColSplit<T, K> SH;
     hipLaunchKernelGGL((wb_column_split_kernel<T, K>), dim3(256), dim3(split_threads<T>()), (unsigned)SH::lds, s,
