@@ -54,6 +54,9 @@ __global__ void __launch_bounds__(kRdmThreads) rdm_kernel(const IncDev* __restri
 #pragma unroll
   for (int t = 0; t < kTilesPerWave; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
   const int64_t nd = d.n_det;
+  // determinant j = a n + b of the chunk: (a0, b0) of its first entry once per
+  // chunk, then one 32-bit division by n per entry (t = b0 + jj < n + 32)
+  int a0 = 0, b0 = 0;
   for (int64_t base = 0; base < nd; base += kRdmChunk) {
     __syncthreads();
     for (int e = threadIdx.x; e < k2p * kRdmChunk; e += blockDim.x) {
@@ -61,7 +64,8 @@ __global__ void __launch_bounds__(kRdmThreads) rdm_kernel(const IncDev* __restri
       const int64_t j = base + jj;
       double v = 0.0;
       if (x < k2 && j < nd) {
-        const int a = (int)(j / n), b = (int)(j % n);
+        const int t = b0 + jj, ta = t / n;
+        const int a = a0 + ta, b = t - ta * n;
         const int p = x / k, q = x % k;
         const int ea = ord[a * k2 + q * k + p];  // E_qp |a>
         if (ea >= 0) {
@@ -84,12 +88,16 @@ __global__ void __launch_bounds__(kRdmThreads) rdm_kernel(const IncDev* __restri
       const int64_t j = base + jj;
       double v = 0.0;
       if (j < nd) {
-        const int a = (int)(j / n), b = (int)(j % n);
+        const int t = b0 + jj, ta = t / n;
+        const int a = a0 + ta, b = t - ta * n;
         v = X[packed(a, b)];
         if (a != b) v *= kRSqrt2;
       }
       cc[jj] = v;
     }
+    b0 += kRdmChunk;  // advance to the next chunk's first entry
+    a0 += b0 / n;
+    b0 %= n;
     __syncthreads();
     if (blockIdx.y == 0 && (int)threadIdx.x < k2) {
       double s = 0.0;
