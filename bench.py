@@ -270,7 +270,11 @@ def large_sigma(torch, ifci, synthetic, n_orb=14, reps=5):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        out[name] = {"ms": ms, "tflops": flops / (ms * 1e-3) / 1e12, "frac_mfma_peak": flops / (ms * 1e-3) / peak}
+        # HBM rate on algorithmic bytes (C read once, sigma written once); the
+        # counted traffic of the same kernels is in the column-sigma profile
+        gbps = out[f"algorithmic_bytes_{name}"] / (ms * 1e-3) / 1e9
+        out[name] = {"ms": ms, "tflops": flops / (ms * 1e-3) / 1e12, "frac_mfma_peak": flops / (ms * 1e-3) / peak,
+                     "algorithmic_GBps": gbps, "frac_hbm_peak_algorithmic": gbps * 1e9 / PEAK["hbm"]}
     plan.close()
     del plan
     torch.cuda.empty_cache()
